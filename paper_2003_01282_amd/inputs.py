@@ -1,0 +1,202 @@
+"""Seeded synthetic graph workloads (shared by the tests, the benchmark and the
+oracle's callers; holds none of the method's arithmetic).
+
+All graphs are undirected and unweighted, returned as symmetric CSR with
+int64 row offsets and int32 column indices, rows sorted, no self-loops and no
+duplicate edges (nnz = 2|E|).  The paper measures on public graphs that are not
+available here; these generators take their shapes instead:
+
+  chung_lu  power-law expected degrees (Chung-Lu), e.g. n=1e4, 5e4 endpoint
+            pairs, degree exponent 2.5;
+  rmat      recursive-matrix graphs (Chakrabarti et al.), scale 22 stands in
+            for LiveJournal/Orkut-sized social graphs, scale 26 for Friendster;
+  er / sbm  Erdos-Renyi and stochastic block model graphs, the small-graph
+            mix of the batched workload (tens to hundreds of nodes, like the
+            graph-classification collections the paper uses).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class CSR:
+    n: int
+    row_ptr: np.ndarray   # int64[n+1]
+    col_idx: np.ndarray   # int32[nnz]
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[-1])
+
+
+def csr_from_pairs(n, u, v):
+    """Undirected pairs (any order, duplicates and self-loops allowed) ->
+    symmetric CSR without self-loops or duplicates."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    lo = np.minimum(u, v)
+    hi = np.maximum(u, v)
+    key = np.unique(lo * n + hi)
+    lo = key // n
+    hi = key - lo * n
+    del key
+    both = np.concatenate([lo * n + hi, hi * n + lo])
+    del lo, hi
+    both.sort()
+    rows = both // n
+    cols = (both - rows * n).astype(np.int32)
+    del both
+    counts = np.bincount(rows, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return CSR(n=n, row_ptr=row_ptr, col_idx=cols)
+
+
+def _rng(seed, *stream):
+    return np.random.default_rng(np.random.SeedSequence([int(seed), *[int(s) for s in stream]]))
+
+
+def chung_lu(n, n_pairs, gamma=2.5, seed=0):
+    """Chung-Lu power-law graph: node i has weight (i+1)^(-1/(gamma-1)); each of
+    n_pairs endpoint pairs draws both ends independently with probability
+    proportional to weight; self-loops and duplicates are dropped."""
+    rng = _rng(seed, 1)
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = np.searchsorted(cdf, rng.random(n_pairs), side="right")
+    v = np.searchsorted(cdf, rng.random(n_pairs), side="right")
+    return csr_from_pairs(n, np.minimum(u, n - 1), np.minimum(v, n - 1))
+
+
+def rmat(scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=0):
+    """R-MAT graph on n = 2^scale nodes from edge_factor * n edge samples.
+    At every level the quadrant is (0,0), (0,1), (1,0), (1,1) with
+    probabilities a, b, c, 1-a-b-c; no noise, ids not permuted."""
+    rng = _rng(seed, 2)
+    n = 1 << scale
+    e = edge_factor * n
+    src = np.zeros(e, dtype=np.int64)
+    dst = np.zeros(e, dtype=np.int64)
+    ab, abc = a + b, a + b + c
+    for _ in range(scale):
+        r = rng.random(e, dtype=np.float32)
+        src <<= 1
+        dst <<= 1
+        src += r >= ab
+        dst += ((r >= a) & (r < ab)) | (r >= abc)
+        del r
+    return csr_from_pairs(n, src, dst)
+
+
+def erdos_renyi(n, p, seed=0):
+    """G(n, p).  Exact Bernoulli draws on the upper triangle for n <= 4096;
+    above that, Binomial(n(n-1)/2, p) uniform pairs (duplicates dropped)."""
+    rng = _rng(seed, 3)
+    if n <= 4096:
+        iu, ju = np.triu_indices(n, 1)
+        keep = rng.random(iu.size) < p
+        return csr_from_pairs(n, iu[keep], ju[keep])
+    m = rng.binomial(n * (n - 1) // 2, p)
+    return csr_from_pairs(n, rng.integers(0, n, m), rng.integers(0, n, m))
+
+
+def sbm(n, k, p_in, p_out, seed=0):
+    """Stochastic block model with k blocks, uniform random labels, edge
+    probability p_in inside a block and p_out across blocks.  Exact Bernoulli
+    draws for n <= 4096, block-pair Binomial sampling above."""
+    rng = _rng(seed, 4)
+    lab = rng.integers(0, k, n)
+    if n <= 4096:
+        iu, ju = np.triu_indices(n, 1)
+        prob = np.where(lab[iu] == lab[ju], p_in, p_out)
+        keep = rng.random(iu.size) < prob
+        return csr_from_pairs(n, iu[keep], ju[keep])
+    members = [np.flatnonzero(lab == b) for b in range(k)]
+    us, vs = [], []
+    for x in range(k):
+        for y in range(x, k):
+            nx, ny = members[x].size, members[y].size
+            pairs = nx * (nx - 1) // 2 if x == y else nx * ny
+            cnt = rng.binomial(pairs, p_in if x == y else p_out)
+            us.append(members[x][rng.integers(0, max(nx, 1), cnt)])
+            vs.append(members[y][rng.integers(0, max(ny, 1), cnt)])
+    return csr_from_pairs(n, np.concatenate(us), np.concatenate(vs))
+
+
+def complete(n):
+    i, j = np.triu_indices(n, 1)
+    return csr_from_pairs(n, i, j)
+
+
+def cycle(n):
+    i = np.arange(n)
+    return csr_from_pairs(n, i, (i + 1) % n)
+
+
+def path(n):
+    i = np.arange(n - 1)
+    return csr_from_pairs(n, i, i + 1)
+
+
+def star(n):
+    return csr_from_pairs(n, np.zeros(n - 1, dtype=np.int64), np.arange(1, n))
+
+
+def from_edges(n, edges):
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    return csr_from_pairs(n, e[:, 0], e[:, 1])
+
+
+def disjoint_union(graphs):
+    """Block-diagonal union: (CSR of the union, node offsets int64[G+1])."""
+    offs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    np.cumsum([g.n for g in graphs], out=offs[1:])
+    nnz = np.zeros(len(graphs) + 1, dtype=np.int64)
+    np.cumsum([g.nnz for g in graphs], out=nnz[1:])
+    row_ptr = np.zeros(int(offs[-1]) + 1, dtype=np.int64)
+    col = np.empty(int(nnz[-1]), dtype=np.int32)
+    for k, g in enumerate(graphs):
+        row_ptr[offs[k] + 1: offs[k + 1] + 1] = g.row_ptr[1:] + nnz[k]
+        col[nnz[k]: nnz[k + 1]] = g.col_idx + np.int32(offs[k])
+    return CSR(n=int(offs[-1]), row_ptr=row_ptr, col_idx=col), offs
+
+
+def small_graph_mix(count, seed=0, n_lo=20, n_hi=500):
+    """Batched workload: `count` graphs, n uniform on [n_lo, n_hi]; even
+    indices Erdos-Renyi with p ~ U[0.05, 0.3], odd indices a 2-5 block SBM
+    (p_in 0.3, p_out 0.02)."""
+    rng = _rng(seed, 5)
+    ns = rng.integers(n_lo, n_hi + 1, count)
+    ps = rng.uniform(0.05, 0.3, count)
+    ks = rng.integers(2, 6, count)
+    out = []
+    for g in range(count):
+        gs = int(seed) * 1_000_003 + g
+        if g % 2 == 0:
+            out.append(erdos_renyi(int(ns[g]), float(ps[g]), seed=gs))
+        else:
+            out.append(sbm(int(ns[g]), int(ks[g]), 0.3, 0.02, seed=gs))
+    return out
+
+
+def closure_graph(idx, seed=0, n_lo=1_000, n_hi=100_000, mean_degree=10.0):
+    """One graph of the closure's training/evaluation population: n
+    log-uniform on [n_lo, n_hi]; family by idx mod 3: Chung-Lu (gamma 2.5),
+    SBM (2-5 blocks, p_in/p_out = 15) or Erdos-Renyi, all with the given
+    expected mean degree."""
+    rng = _rng(seed, 6, idx)
+    n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+    gs = int(seed) * 7_919 + idx
+    fam = idx % 3
+    if fam == 0:
+        return chung_lu(n, int(mean_degree * n / 2), 2.5, seed=gs)
+    if fam == 1:
+        k = int(rng.integers(2, 6))
+        # mean degree = (n/k) p_in + (n - n/k) p_out with p_in = 15 p_out
+        p_out = mean_degree / (15.0 * n / k + (n - n / k))
+        return sbm(n, k, min(15.0 * p_out, 1.0), p_out, seed=gs)
+    return erdos_renyi(n, mean_degree / (n - 1), seed=gs)
