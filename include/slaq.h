@@ -1,0 +1,153 @@
+/*
+ * slaq.h -- C ABI of libslaq.so, stochastic Lanczos quadrature (SLQ) of graph
+ * Laplacian spectral functions on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is SLaQ (Tsitsulin, Munkhoeva, Perozzi, "Just SLaQ When You
+ * Approximate: Accurate Spectral Distances for Web-Scale Graphs", WWW 2020,
+ * arXiv 2003.01282): tr f(L) is estimated by Hutchinson's estimator over nv
+ * random probes (§3.1, eq. "trace"); each quadratic form v^T f(L) v by the
+ * m-point Gauss rule whose nodes and weights are the eigenvalues of the
+ * Lanczos tridiagonal T and the squared first components of its eigenvectors
+ * (§3.1, eq. "quadratic"); the estimate is Gamma = n/nv sum_p sum_k
+ * tau_pk^2 f(theta_pk) (§3.1, eq. "slq"; Algorithm 1).  The spectral
+ * functions are the heat trace of NetLSD (§2.2, eq. "heat-trace"), its wave
+ * counterpart, and the von Neumann graph entropy of §2.1.
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer owned by the caller (e.g. a
+ *    torch tensor's storage).  The library never allocates, frees or keeps
+ *    caller memory beyond the documented lifetime of a handle.
+ *  - Every call is asynchronous and ordered on `stream` (a hipStream_t, NULL
+ *    = the default stream); outputs are valid once that stream has reached
+ *    the call.  Only slaq_graph_info and a build with SLAQ_FLAG_CHECK wait.
+ *  - Argument errors detectable on the host (NULL pointers, sizes out of
+ *    range, a workspace that is too small) return an error before anything
+ *    is enqueued.  slaq_last_error() then describes it (thread-local).
+ *  - No C++ exception crosses this boundary.
+ *  - Graph layout: CSR of a symmetric adjacency matrix A with positive
+ *    weights (§2): row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing,
+ *    row_ptr[n] = nnz), col_idx int32[nnz] in [0, n), optional weights
+ *    float[nnz] (NULL = every edge has weight 1).  Both directions of an
+ *    undirected edge are stored, so nnz = 2|E| for a loop-free graph.
+ *  - Probe vectors are FP32; alpha/beta reductions accumulate in FP64; the
+ *    tridiagonal eigensolve and the quadrature are FP64.
+ */
+#ifndef SLAQ_H
+#define SLAQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLAQ_OK = 0,
+    SLAQ_ERR_INVALID_ARG = 1,   /* NULL pointer, size out of range, bad enum */
+    SLAQ_ERR_NOT_SYMMETRIC = 2, /* SLAQ_FLAG_CHECK found (i,j) without (j,i) */
+    SLAQ_ERR_NUMERIC = 3,       /* weight <= 0 or not finite (SLAQ_FLAG_CHECK) */
+    SLAQ_ERR_WORKSPACE = 4,     /* workspace smaller than the size query says */
+    SLAQ_ERR_HIP = 5,           /* a HIP runtime call failed */
+    SLAQ_ERR_UNSUPPORTED = 6,   /* valid request this build does not serve */
+    SLAQ_ERR_BAD_CSR = 7        /* SLAQ_FLAG_CHECK: row_ptr / col_idx malformed */
+} slaq_status;
+
+/* Which Laplacian (§2): L = I - D^-1/2 A D^-1/2 (isolated nodes get a zero row
+ * and column, so they add eigenvalue 0), or L = D - A. */
+enum { SLAQ_LAP_NORMALIZED = 0, SLAQ_LAP_COMBINATORIAL = 1 };
+
+/* Which trace signature: heat h_t = tr exp(-tL) (§2.2, eq. "heat-trace"), or
+ * wave w_t = Re tr exp(-itL) = sum_i cos(t lambda_i). */
+enum { SLAQ_SIG_HEAT = 0, SLAQ_SIG_WAVE = 1 };
+
+/* slaq_build_graph flags */
+enum { SLAQ_FLAG_CHECK = 1u };
+
+/* Size limits of this build. */
+enum { SLAQ_MAX_PROBES = 4096, SLAQ_MAX_STEPS = 64 };
+
+typedef struct slaq_graph_s* slaq_graph_t;
+
+/* Bytes of device scratch slaq_build_graph needs for a graph of n nodes and
+ * nnz stored entries. */
+slaq_status slaq_graph_scratch_bytes(int64_t n, int64_t nnz, size_t* bytes);
+
+/* Degrees D_ii = sum_j A_ij, the diagonal scale of the Laplacian and the
+ * graph statistics (§2; tr L per §2.1's density matrix).
+ *   dinv_out  float[n], caller-owned: D_ii^-1/2 (0 for an isolated node) for
+ *             the normalized Laplacian, D_ii for the combinatorial one.
+ *   scratch   device memory of slaq_graph_scratch_bytes(); holds tr(L), the
+ *             number of isolated nodes and max_i D_ii.
+ * The handle stores the pointers it was given: row_ptr, col_idx, weights,
+ * dinv_out and scratch must stay valid and unchanged until
+ * slaq_graph_destroy.  With SLAQ_FLAG_CHECK the call validates the CSR
+ * (monotone row_ptr, columns in range, symmetric pattern and weights,
+ * positive finite weights) and waits for the result. */
+slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                             const int32_t* col_idx, const float* weights,
+                             int laplacian, unsigned flags, float* dinv_out,
+                             void* scratch, size_t scratch_bytes, void* stream,
+                             slaq_graph_t* out);
+
+/* Waits for the build on its stream and reports n, nnz, tr(L) (number of
+ * non-isolated nodes, or sum_i D_ii), the isolated-node count and max D_ii.
+ * Any output pointer may be NULL. */
+slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* trace,
+                            int64_t* n_isolated, double* max_degree);
+
+/* Frees the host handle (never caller memory). */
+slaq_status slaq_graph_destroy(slaq_graph_t g);
+
+/* Bytes of device workspace slaq_lanczos needs for nv probes. */
+slaq_status slaq_lanczos_workspace(slaq_graph_t g, int nv, int m, size_t* bytes);
+
+/* m steps of the Lanczos three-term recurrence (§3.1) on nv Rademacher probes
+ * at once, without reorthogonalization.  Probe p's start vector is
+ * q1[i] = v[i,p] / sqrt(n) with v[i,p] = +-1 given by bit (p mod 64) of
+ * SplitMix64 output number 64*i + (p div 64) + 1 for `seed` (a set bit gives
+ * -1), so q1 has unit norm (§3.1's "starting unit-vector").  Per probe and
+ * step j = 1..m:
+ *     w = L q_j - beta_{j-1} q_{j-1};  alpha_j = q_j . w;
+ *     beta_j = || w - alpha_j q_j ||;   q_{j+1} = (w - alpha_j q_j) / beta_j.
+ * Outputs (device, caller-owned, row-major by probe):
+ *   alpha, beta  double[nv*m]: T_p = tridiag(beta, alpha, beta); beta[p*m+j-1]
+ *                couples q_j and q_{j+1} (the last one is kept).
+ *   steps        int32[nv]: Lanczos steps taken; < m when the Krylov space of
+ *                the probe became invariant (beta_j <= 1e-6 * spectral bound,
+ *                i.e. 2 or 2 max D_ii); entries past steps[p] are 0.  This is
+ *                not an error.
+ * workspace: device memory of slaq_lanczos_workspace() bytes; 1 <= nv <=
+ * SLAQ_MAX_PROBES, 1 <= m <= SLAQ_MAX_STEPS. */
+slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha,
+                         double* beta, int32_t* steps, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* Gauss nodes and weights (§3.1, eq. "quadratic"): theta[p*m+k] are the
+ * eigenvalues of T_p (size steps[p]) and tau2[p*m+k] the squared first
+ * components of its normalized eigenvectors; entries k >= steps[p] are 0.
+ * FP64 implicit-shift QL per probe. */
+slaq_status slaq_ritz(const double* alpha, const double* beta, const int32_t* steps,
+                      int nv, int m, double* theta, double* tau2, void* stream);
+
+/* Trace signature Gamma_f = n/nv sum_p sum_k tau2 f(theta) (§3.1, eq. "slq")
+ * at the nt time scales t[0..nt) (device double[nt]) for f = exp(-t x)
+ * (SLAQ_SIG_HEAT) or cos(t x) (SLAQ_SIG_WAVE); out double[nt]. */
+slaq_status slaq_signature(const double* theta, const double* tau2, int nv, int m,
+                           int64_t n, const double* t, int nt, int kind, double* out,
+                           void* stream);
+
+/* Von Neumann graph entropy H = -tr g(L / tr L), g(x) = x ln x (0 for x <= 0)
+ * (§2.1 Definition; Algorithm 1's SLaQ_VNGE), estimated as
+ * -n/nv sum_p sum_k tau2 g(theta / tr L) with n and tr L taken from the graph
+ * (on the device, no wait); out double[1]. */
+slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, int nv,
+                      int m, double* out, void* stream);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* slaq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLAQ_H */

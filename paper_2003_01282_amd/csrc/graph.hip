@@ -1,0 +1,269 @@
+// Graph build: degrees, the Laplacian's diagonal scale and graph statistics
+// (paper §2: D_ii = sum_j A_ij, L = D - A, normalized L = I - D^-1/2 A D^-1/2;
+// §2.1: the density matrix is L / tr L).
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+namespace slaq {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+enum : unsigned {
+    kCheckBadRowPtr = 1u,
+    kCheckBadCol = 2u,
+    kCheckUnsorted = 4u,
+    kCheckAsymmetric = 8u,
+    kCheckBadWeight = 16u,
+};
+
+// One thread per row, grid-stride.  Degree is a count (unweighted, exact) or a
+// double sum of weights.  Each block writes one partial (fixed-order reduce).
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(256) degree_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                     const float* __restrict__ w, int laplacian,
+                                                     float* __restrict__ diag,
+                                                     BuildPartial* __restrict__ part) {
+    double dmax = 0.0, dsum = 0.0;
+    long long nz = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = rp[i], e = rp[i + 1];
+        double d;
+        if (WEIGHTED) {
+            d = 0.0;
+            for (int64_t k = s; k < e; ++k) d += (double)w[k];
+        } else {
+            d = (double)(e - s);
+        }
+        float out;
+        if (laplacian == SLAQ_LAP_NORMALIZED)
+            out = d > 0.0 ? (float)(1.0 / sqrt(d)) : 0.0f;
+        else
+            out = (float)d;
+        diag[i] = out;
+        dmax = fmax(dmax, d);
+        dsum += d;
+        nz += d > 0.0 ? 1 : 0;
+    }
+    __shared__ double smax[256], ssum[256];
+    __shared__ long long snz[256];
+    const int t = threadIdx.x;
+    smax[t] = dmax;
+    ssum[t] = dsum;
+    snz[t] = nz;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            smax[t] = fmax(smax[t], smax[t + off]);
+            ssum[t] += ssum[t + off];
+            snz[t] += snz[t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        part[blockIdx.x].max_degree = smax[0];
+        part[blockIdx.x].sum_degree = ssum[0];
+        part[blockIdx.x].nonisolated = snz[0];
+    }
+}
+
+__global__ void __launch_bounds__(256) stats_kernel(int64_t n, int nparts, int laplacian,
+                                                    const BuildPartial* __restrict__ part,
+                                                    GraphStats* __restrict__ st) {
+    __shared__ double smax[256], ssum[256];
+    __shared__ long long snz[256];
+    const int t = threadIdx.x;
+    double dmax = 0.0, dsum = 0.0;
+    long long nz = 0;
+    for (int b = t; b < nparts; b += 256) {
+        dmax = fmax(dmax, part[b].max_degree);
+        dsum += part[b].sum_degree;
+        nz += part[b].nonisolated;
+    }
+    smax[t] = dmax;
+    ssum[t] = dsum;
+    snz[t] = nz;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            smax[t] = fmax(smax[t], smax[t + off]);
+            ssum[t] += ssum[t + off];
+            snz[t] += snz[t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        st->max_degree = smax[0];
+        st->sum_degree = ssum[0];
+        st->n_isolated = (long long)n - snz[0];
+        st->trace = laplacian == SLAQ_LAP_NORMALIZED ? (double)snz[0] : ssum[0];
+        st->check = 0u;
+    }
+}
+
+// SLAQ_FLAG_CHECK: one thread per row.  Rows must be strictly increasing in
+// column (sorted, no duplicates) so the transpose entry is found by bisection.
+__global__ void __launch_bounds__(256) check_kernel(int64_t n, int64_t nnz,
+                                                    const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const float* __restrict__ w,
+                                                    GraphStats* __restrict__ st) {
+    unsigned bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = rp[i], e = rp[i + 1];
+        if (s < 0 || (i == 0 && s != 0) || e < s || e > nnz || (i == n - 1 && e != nnz)) {
+            bad |= kCheckBadRowPtr;
+            continue;
+        }
+        int32_t prev = -1;
+        for (int64_t k = s; k < e; ++k) {
+            const int32_t j = col[k];
+            if (j < 0 || (int64_t)j >= n) {
+                bad |= kCheckBadCol;
+                continue;
+            }
+            if (j <= prev) bad |= kCheckUnsorted;
+            prev = j;
+            if (w) {
+                const float x = w[k];
+                if (!(x > 0.0f) || !isfinite(x)) bad |= kCheckBadWeight;
+            }
+            // bisection for i in row j
+            int64_t lo = rp[j], hi = rp[j + 1];
+            if (lo < 0 || hi > nnz || hi < lo) {
+                bad |= kCheckBadRowPtr;
+                continue;
+            }
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if ((int64_t)col[mid] < i) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= rp[j + 1] || (int64_t)col[lo] != i) bad |= kCheckAsymmetric;
+            else if (w && w[lo] != w[k]) bad |= kCheckAsymmetric;
+        }
+    }
+    if (bad) atomicOr(&st->check, bad);
+}
+
+}  // namespace slaq
+
+using namespace slaq;
+
+extern "C" {
+
+const char* slaq_last_error(void) { return g_err; }
+
+slaq_status slaq_graph_scratch_bytes(int64_t n, int64_t nnz, size_t* bytes) {
+    SLAQ_REQUIRE(bytes, SLAQ_ERR_INVALID_ARG, "bytes is NULL");
+    SLAQ_REQUIRE(n > 0 && nnz >= 0, SLAQ_ERR_INVALID_ARG, "need n > 0 and nnz >= 0");
+    *bytes = align_up(sizeof(GraphStats), 256) + align_up(sizeof(BuildPartial) * kBuildBlocks, 256);
+    return SLAQ_OK;
+}
+
+slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                             const float* weights, int laplacian, unsigned flags, float* dinv_out,
+                             void* scratch, size_t scratch_bytes, void* stream, slaq_graph_t* out) {
+    clear_error();
+    SLAQ_REQUIRE(out, SLAQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    SLAQ_REQUIRE(n > 0, SLAQ_ERR_INVALID_ARG, "n must be positive (got %lld)", (long long)n);
+    SLAQ_REQUIRE(n < (int64_t)INT32_MAX, SLAQ_ERR_UNSUPPORTED, "n must fit int32 column indices");
+    SLAQ_REQUIRE(nnz >= 0, SLAQ_ERR_INVALID_ARG, "nnz must be >= 0");
+    SLAQ_REQUIRE(row_ptr && dinv_out && scratch, SLAQ_ERR_INVALID_ARG,
+                 "row_ptr, dinv_out and scratch must be non-NULL");
+    SLAQ_REQUIRE(nnz == 0 || col_idx, SLAQ_ERR_INVALID_ARG, "col_idx is NULL");
+    SLAQ_REQUIRE(laplacian == SLAQ_LAP_NORMALIZED || laplacian == SLAQ_LAP_COMBINATORIAL,
+                 SLAQ_ERR_INVALID_ARG, "unknown laplacian kind %d", laplacian);
+    SLAQ_REQUIRE((flags & ~(unsigned)SLAQ_FLAG_CHECK) == 0, SLAQ_ERR_INVALID_ARG, "unknown flags");
+    size_t need = 0;
+    slaq_graph_scratch_bytes(n, nnz, &need);
+    SLAQ_REQUIRE(scratch_bytes >= need, SLAQ_ERR_WORKSPACE, "graph scratch needs %zu bytes, got %zu",
+                 need, scratch_bytes);
+    SLAQ_REQUIRE(((uintptr_t)scratch & 255) == 0, SLAQ_ERR_INVALID_ARG, "scratch must be 256-byte aligned");
+
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)scratch;
+    GraphStats* stats = (GraphStats*)base;
+    BuildPartial* part = (BuildPartial*)(base + align_up(sizeof(GraphStats), 256));
+
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > kBuildBlocks) blocks = kBuildBlocks;
+
+    if (flags & SLAQ_FLAG_CHECK) {
+        // validate before anything reads the CSR through row_ptr
+        SLAQ_HIP(hipMemsetAsync(&stats->check, 0, sizeof(unsigned), st));
+        hipLaunchKernelGGL(check_kernel, dim3(blocks), dim3(256), 0, st, n, nnz, row_ptr, col_idx,
+                           weights, stats);
+        SLAQ_LAUNCHED();
+        unsigned found = 0;
+        SLAQ_HIP(hipMemcpyAsync(&found, &stats->check, sizeof(found), hipMemcpyDeviceToHost, st));
+        SLAQ_HIP(hipStreamSynchronize(st));
+        SLAQ_REQUIRE(!(found & (kCheckBadRowPtr | kCheckBadCol | kCheckUnsorted)), SLAQ_ERR_BAD_CSR,
+                     "CSR check failed (flags 0x%x: 1 row_ptr, 2 column range, 4 unsorted/duplicate)",
+                     found);
+        SLAQ_REQUIRE(!(found & kCheckBadWeight), SLAQ_ERR_NUMERIC, "a weight is <= 0 or not finite");
+        SLAQ_REQUIRE(!(found & kCheckAsymmetric), SLAQ_ERR_NOT_SYMMETRIC,
+                     "adjacency is not symmetric (pattern or weights)");
+    }
+
+    if (weights)
+        hipLaunchKernelGGL(degree_kernel<true>, dim3(blocks), dim3(256), 0, st, n, row_ptr, weights,
+                           laplacian, dinv_out, part);
+    else
+        hipLaunchKernelGGL(degree_kernel<false>, dim3(blocks), dim3(256), 0, st, n, row_ptr, weights,
+                           laplacian, dinv_out, part);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(256), 0, st, n, blocks, laplacian, part, stats);
+    SLAQ_LAUNCHED();
+
+    slaq_graph_s* g = new (std::nothrow) slaq_graph_s;
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "out of host memory");
+    g->n = n;
+    g->nnz = nnz;
+    g->row_ptr = row_ptr;
+    g->col_idx = col_idx;
+    g->weights = weights;
+    g->laplacian = laplacian;
+    g->diag = dinv_out;
+    g->stats = stats;
+    g->partials = part;
+    g->stream = st;
+    *out = g;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* trace,
+                            int64_t* n_isolated, double* max_degree) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    GraphStats hs;
+    SLAQ_HIP(hipMemcpyAsync(&hs, g->stats, sizeof(hs), hipMemcpyDeviceToHost, g->stream));
+    SLAQ_HIP(hipStreamSynchronize(g->stream));
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (trace) *trace = hs.trace;
+    if (n_isolated) *n_isolated = hs.n_isolated;
+    if (max_degree) *max_degree = hs.max_degree;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_destroy(slaq_graph_t g) {
+    delete g;
+    return SLAQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Gauss rule per probe and the SLQ estimate (paper §3.1, eqs. "quadratic" and
+// "slq"; Algorithm 1's eigh(T) and the final weighted sum), all in FP64.
+#include <cmath>
+
+#include "common.hpp"
+#include "tridiag.hpp"
+
+namespace slaq {
+
+// One thread per probe; T_p lives in LDS interleaved across the block
+// (stride = blockDim.x, 3 * blockDim.x * m doubles).
+__global__ void __launch_bounds__(64) ritz_kernel(const double* __restrict__ alpha,
+                                                          const double* __restrict__ beta,
+                                                          const int32_t* __restrict__ steps, int nv, int m,
+                                                          double* __restrict__ theta,
+                                                          double* __restrict__ tau2) {
+    extern __shared__ double lds[];
+    const int t = threadIdx.x, B = blockDim.x;
+    const int p = blockIdx.x * B + t;
+    double* d = lds + t;
+    double* e = lds + B * m + t;
+    double* u = lds + 2 * B * m + t;
+    if (p >= nv) return;
+    int k = steps[p];
+    k = k < 0 ? 0 : (k > m ? m : k);
+    for (int i = 0; i < k; ++i) {
+        d[i * B] = alpha[(int64_t)p * m + i];
+        e[i * B] = i + 1 < k ? beta[(int64_t)p * m + i] : 0.0;
+    }
+    tridiag_eig_first_row(d, e, u, k, B);
+    for (int i = 0; i < m; ++i) {
+        const bool in = i < k;
+        const double ui = in ? u[i * B] : 0.0;
+        theta[(int64_t)p * m + i] = in ? d[i * B] : 0.0;
+        tau2[(int64_t)p * m + i] = ui * ui;
+    }
+}
+
+// Block b evaluates out[b] = n/nv sum_{p,k} tau2 f(t_b theta); threads stride
+// over the nv*m pairs and reduce in a fixed tree (deterministic).
+__global__ void __launch_bounds__(256) signature_kernel(const double* __restrict__ theta,
+                                                        const double* __restrict__ tau2, int count,
+                                                        double scale, const double* __restrict__ tgrid,
+                                                        int kind, double* __restrict__ out) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const double tt = tgrid[b];
+    double acc = 0.0;
+    for (int i = tid; i < count; i += 256) {
+        const double w = tau2[i];
+        const double x = theta[i];
+        acc += w * (kind == SLAQ_SIG_HEAT ? exp(-tt * x) : cos(tt * x));
+    }
+    __shared__ double red[256];
+    red[tid] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) out[b] = scale * red[0];
+}
+
+// H = -n/nv sum tau2 g(theta / tr L), g(x) = x ln x for x > 0, else 0.
+__global__ void __launch_bounds__(256) vnge_kernel(const double* __restrict__ theta,
+                                                   const double* __restrict__ tau2, int count, double scale,
+                                                   const GraphStats* __restrict__ st, double* __restrict__ out) {
+    const int tid = threadIdx.x;
+    const double c = st->trace;
+    double acc = 0.0;
+    if (c > 0.0) {
+        for (int i = tid; i < count; i += 256) {
+            const double x = theta[i] / c;
+            if (x > 0.0) acc += tau2[i] * (x * log(x));
+        }
+    }
+    __shared__ double red[256];
+    red[tid] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = -scale * red[0];
+}
+
+}  // namespace slaq
+
+using namespace slaq;
+
+extern "C" {
+
+slaq_status slaq_ritz(const double* alpha, const double* beta, const int32_t* steps, int nv, int m,
+                      double* theta, double* tau2, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(alpha && beta && steps && theta && tau2, SLAQ_ERR_INVALID_ARG, "NULL pointer argument");
+    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
+                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
+    const int B = m <= 32 ? 64 : 32;  // keeps the LDS tile at <= 48 KB
+    const size_t lds = (size_t)3 * B * m * sizeof(double);
+    hipLaunchKernelGGL(ritz_kernel, dim3((nv + B - 1) / B), dim3(B), lds,
+                       (hipStream_t)stream, alpha, beta, steps, nv, m, theta, tau2);
+    SLAQ_LAUNCHED();
+    return SLAQ_OK;
+}
+
+slaq_status slaq_signature(const double* theta, const double* tau2, int nv, int m, int64_t n,
+                           const double* t, int nt, int kind, double* out, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(theta && tau2 && t && out, SLAQ_ERR_INVALID_ARG, "NULL pointer argument");
+    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
+                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
+    SLAQ_REQUIRE(n > 0, SLAQ_ERR_INVALID_ARG, "n must be positive");
+    SLAQ_REQUIRE(nt >= 1 && nt <= 65535, SLAQ_ERR_INVALID_ARG, "nt must be in [1, 65535]");
+    SLAQ_REQUIRE(kind == SLAQ_SIG_HEAT || kind == SLAQ_SIG_WAVE, SLAQ_ERR_INVALID_ARG, "unknown signature kind");
+    const double scale = (double)n / (double)nv;
+    hipLaunchKernelGGL(signature_kernel, dim3(nt), dim3(256), 0, (hipStream_t)stream, theta, tau2, nv * m, scale,
+                       t, kind, out);
+    SLAQ_LAUNCHED();
+    return SLAQ_OK;
+}
+
+slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, int nv, int m, double* out,
+                      void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(g && theta && tau2 && out, SLAQ_ERR_INVALID_ARG, "NULL pointer argument");
+    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
+                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
+    const double scale = (double)g->n / (double)nv;
+    hipLaunchKernelGGL(vnge_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, theta, tau2, nv * m, scale,
+                       g->stats, out);
+    SLAQ_LAUNCHED();
+    return SLAQ_OK;
+}
+
+}  // extern "C"

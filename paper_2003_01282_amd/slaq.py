@@ -1,0 +1,212 @@
+"""Thin Python binding of libslaq.so (argument marshalling only).
+
+Every computation runs in the HIP library; torch supplies device memory and
+the current stream.  Names follow the C ABI in include/slaq.h.  The library
+must be built (paper_2003_01282_amd.build); there is no fallback path.
+"""
+import ctypes
+from pathlib import Path
+
+import torch
+
+LIB_PATH = Path(__file__).resolve().parent / "libslaq.so"
+
+SLAQ_LAP_NORMALIZED = 0
+SLAQ_LAP_COMBINATORIAL = 1
+SLAQ_SIG_HEAT = 0
+SLAQ_SIG_WAVE = 1
+SLAQ_FLAG_CHECK = 1
+SLAQ_MAX_PROBES = 4096
+SLAQ_MAX_STEPS = 64
+
+STATUS = {
+    0: "SLAQ_OK", 1: "SLAQ_ERR_INVALID_ARG", 2: "SLAQ_ERR_NOT_SYMMETRIC", 3: "SLAQ_ERR_NUMERIC",
+    4: "SLAQ_ERR_WORKSPACE", 5: "SLAQ_ERR_HIP", 6: "SLAQ_ERR_UNSUPPORTED", 7: "SLAQ_ERR_BAD_CSR",
+}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_sz = ctypes.c_size_t
+
+# name -> argument types (all return slaq_status except slaq_last_error)
+SIGNATURES = {
+    "slaq_graph_scratch_bytes": [_i64, _i64, ctypes.POINTER(_sz)],
+    "slaq_build_graph": [_i64, _i64, _vp, _vp, _vp, _int, ctypes.c_uint, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)],
+    "slaq_graph_info": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
+    "slaq_graph_destroy": [_vp],
+    "slaq_lanczos_workspace": [_vp, _int, _int, ctypes.POINTER(_sz)],
+    "slaq_lanczos": [_vp, _int, _int, ctypes.c_uint64, _vp, _vp, _vp, _vp, _sz, _vp],
+    "slaq_ritz": [_vp, _vp, _vp, _int, _int, _vp, _vp, _vp],
+    "slaq_signature": [_vp, _vp, _int, _int, _i64, _vp, _int, _int, _vp, _vp],
+    "slaq_vnge": [_vp, _vp, _vp, _int, _int, _vp, _vp],
+}
+
+_LIB = None
+
+
+class SlaqError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib():
+    """Loads libslaq.so once; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2003_01282_amd.build`")
+        L = ctypes.CDLL(str(LIB_PATH))
+        for name, args in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.slaq_last_error.argtypes = []
+        L.slaq_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != 0:
+        raise SlaqError(status, lib().slaq_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _dev(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _empty_aligned(nbytes, device):
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class Graph:
+    """Handle returned by build_graph; keeps its device buffers alive."""
+
+    def __init__(self, handle, n, nnz, laplacian, keep):
+        self.handle = handle
+        self.n = n
+        self.nnz = nnz
+        self.laplacian = laplacian
+        self._keep = keep
+
+    @property
+    def dinv(self):
+        return self._keep["dinv"]
+
+    def info(self):
+        n, nnz, iso = _i64(), _i64(), _i64()
+        tr, mx = ctypes.c_double(), ctypes.c_double()
+        _check(lib().slaq_graph_info(self.handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(tr),
+                                     ctypes.byref(iso), ctypes.byref(mx)))
+        return {"n": n.value, "nnz": nnz.value, "trace": tr.value, "n_isolated": iso.value,
+                "max_degree": mx.value}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.slaq_graph_destroy(h)
+            self.handle = None
+
+
+def build_graph(row_ptr, col_idx, weights=None, laplacian=SLAQ_LAP_NORMALIZED, check=False, stream=None):
+    """slaq_build_graph on device CSR tensors (int64 row_ptr, int32 col_idx,
+    optional float32 weights)."""
+    _dev(row_ptr, torch.int64, "row_ptr")
+    _dev(col_idx, torch.int32, "col_idx")
+    if weights is not None:
+        _dev(weights, torch.float32, "weights")
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    dev = row_ptr.device
+    nbytes = _sz()
+    _check(lib().slaq_graph_scratch_bytes(n, nnz, ctypes.byref(nbytes)))
+    dinv = torch.empty(n, dtype=torch.float32, device=dev)
+    scratch = _empty_aligned(nbytes.value, dev)
+    h = _vp()
+    _check(lib().slaq_build_graph(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(weights), laplacian,
+                                  SLAQ_FLAG_CHECK if check else 0, _ptr(dinv), _ptr(scratch), nbytes.value,
+                                  _stream(stream), ctypes.byref(h)))
+    keep = {"row_ptr": row_ptr, "col_idx": col_idx, "weights": weights, "dinv": dinv, "scratch": scratch}
+    return Graph(h, n, nnz, laplacian, keep)
+
+
+def lanczos_workspace(g, nv, m):
+    b = _sz()
+    _check(lib().slaq_lanczos_workspace(g.handle, nv, m, ctypes.byref(b)))
+    return b.value
+
+
+def lanczos(g, nv, m, seed, workspace=None, out=None, stream=None):
+    """slaq_lanczos -> (alpha[nv, m] f64, beta[nv, m] f64, steps[nv] i32)."""
+    dev = g._keep["row_ptr"].device
+    need = lanczos_workspace(g, nv, m)
+    if workspace is None:
+        workspace = _empty_aligned(need, dev)
+    if out is None:
+        out = (torch.empty((nv, m), dtype=torch.float64, device=dev),
+               torch.empty((nv, m), dtype=torch.float64, device=dev),
+               torch.empty(nv, dtype=torch.int32, device=dev))
+    alpha, beta, steps = out
+    _check(lib().slaq_lanczos(g.handle, nv, m, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(alpha), _ptr(beta),
+                              _ptr(steps), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return alpha, beta, steps
+
+
+def ritz(alpha, beta, steps, out=None, stream=None):
+    """slaq_ritz -> (theta[nv, m], tau2[nv, m])."""
+    nv, m = alpha.shape
+    _dev(alpha, torch.float64, "alpha")
+    _dev(beta, torch.float64, "beta")
+    _dev(steps, torch.int32, "steps")
+    if out is None:
+        out = (torch.empty_like(alpha), torch.empty_like(alpha))
+    theta, tau2 = out
+    _check(lib().slaq_ritz(_ptr(alpha), _ptr(beta), _ptr(steps), nv, m, _ptr(theta), _ptr(tau2),
+                           _stream(stream)))
+    return theta, tau2
+
+
+def signature(theta, tau2, n, t, kind=SLAQ_SIG_HEAT, out=None, stream=None):
+    """slaq_signature -> double[nt] (heat or wave trace at the times t)."""
+    nv, m = theta.shape
+    _dev(t, torch.float64, "t")
+    if out is None:
+        out = torch.empty(t.numel(), dtype=torch.float64, device=theta.device)
+    _check(lib().slaq_signature(_ptr(theta), _ptr(tau2), nv, m, n, _ptr(t), t.numel(), kind, _ptr(out),
+                                _stream(stream)))
+    return out
+
+
+def vnge(g, theta, tau2, out=None, stream=None):
+    """slaq_vnge -> double[1]."""
+    nv, m = theta.shape
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=theta.device)
+    _check(lib().slaq_vnge(g.handle, _ptr(theta), _ptr(tau2), nv, m, _ptr(out), _stream(stream)))
+    return out
+
+
+def to_device(csr, device="cuda"):
+    """Host CSR (numpy) -> device tensors (row_ptr int64, col_idx int32)."""
+    rp = torch.from_numpy(csr.row_ptr).to(device)
+    ci = torch.from_numpy(csr.col_idx).to(device)
+    return rp, ci
