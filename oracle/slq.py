@@ -237,7 +237,10 @@ def xlogx(x):
 def vnge(theta, tau2, n, trace):
     """H = -tr g(L / tr L) (§2.1 Definition on the density matrix L / tr(L);
     Algorithm 1 applies slq to that matrix).  The minus sign follows the
-    Definition (Algorithm 1 omits it)."""
+    Definition (Algorithm 1 omits it).  A graph without edges has L = 0 and no
+    density matrix; its entropy is taken as 0."""
+    if trace <= 0:
+        return 0.0
     return -quadrature(theta, tau2, n, lambda x: xlogx(x / trace))
 
 

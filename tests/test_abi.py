@@ -1,0 +1,52 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/slaq.h declares, and rejects bad arguments on the host before any
+device work (no GPU is touched by these calls)."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_2003_01282_amd import slaq as S
+
+HEADER = Path(__file__).resolve().parents[1] / "include" / "slaq.h"
+
+
+def declared_functions():
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    return sorted(set(re.findall(r"\b(slaq_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_named_entry_points():
+    names = declared_functions()
+    for required in ("slaq_build_graph", "slaq_lanczos", "slaq_signature", "slaq_vnge", "slaq_ritz"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = S.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    for name in S.SIGNATURES:
+        assert name in declared_functions(), name
+
+
+def test_host_side_argument_errors():
+    L = S.lib()
+    b = ctypes.c_size_t()
+    assert L.slaq_graph_scratch_bytes(0, 0, ctypes.byref(b)) == 1
+    assert L.slaq_graph_scratch_bytes(10, -1, ctypes.byref(b)) == 1
+    assert L.slaq_graph_scratch_bytes(10, 20, ctypes.byref(b)) == 0 and b.value > 0
+    assert L.slaq_lanczos_workspace(None, 4, 4, ctypes.byref(b)) == 1
+    h = ctypes.c_void_p()
+    # NULL row_ptr: rejected before anything is enqueued
+    assert L.slaq_build_graph(10, 20, None, None, None, 0, 0, None, None, 0, None, ctypes.byref(h)) == 1
+    assert b"non-NULL" in L.slaq_last_error()
+    assert L.slaq_ritz(None, None, None, 4, 4, None, None, None) == 1
+    assert L.slaq_signature(None, None, 4, 4, 10, None, 8, 0, None, None) == 1
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        S.build_graph(torch.zeros(3, dtype=torch.int64), torch.zeros(2, dtype=torch.int32))

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs (same graphs, same SplitMix64 probes)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import slq as O
+from paper_2003_01282_amd import inputs
+from paper_2003_01282_amd import slaq as S
+
+from gpu_helpers import assert_signature_parity, gpu_run, oracle_run
+from test_oracle_pins import load_fig1
+
+pytestmark = pytest.mark.gpu
+
+T256 = O.t_grid(256)
+
+
+def header(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+def test_chung_lu_small_config():
+    # Chung-Lu power law, n=1e4, 5e4 endpoint pairs, nv=10, m=15, 256 t + VNGE
+    header("chung_lu n=1e4 nv=10 m=15")
+    csr = inputs.chung_lu(10_000, 50_000, 2.5, seed=1)
+    gpu = gpu_run(csr, 10, 15, 2024, T256)
+    ora = oracle_run(csr, 10, 15, 2024, T256)
+    assert gpu["info"]["n_isolated"] == ora["graph"].n_isolated
+    assert gpu["info"]["trace"] == ora["graph"].trace
+    np.testing.assert_allclose(gpu["dinv"], ora["graph"].dinv, rtol=1e-7)
+    assert np.array_equal(gpu["steps"], ora["steps"])
+    np.testing.assert_allclose(gpu["alpha"], ora["alpha"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(gpu["beta"], ora["beta"], rtol=1e-5, atol=1e-6)
+    rh, rw = assert_signature_parity(gpu, ora, csr.n, "C1")
+    print(f"heat rel {rh:.2e} wave |d|/n {rw:.2e}")
+
+
+@pytest.mark.parametrize("nv", [1, 3, 64, 100, 130, 300])
+def test_probe_counts_and_tiles(nv):
+    # ragged ld (nv not a multiple of 4), several SplitMix64 words, two tiles
+    header(f"ER n=3000 nv={nv}")
+    csr = inputs.erdos_renyi(3000, 0.004, seed=nv)
+    gpu = gpu_run(csr, nv, 12, 77, T256[::8])
+    ora = oracle_run(csr, nv, 12, 77, T256[::8])
+    assert np.array_equal(gpu["steps"], ora["steps"])
+    np.testing.assert_allclose(gpu["alpha"], ora["alpha"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(gpu["beta"], ora["beta"], rtol=1e-5, atol=1e-6)
+    assert_signature_parity(gpu, ora, csr.n, f"nv={nv}")
+
+
+@pytest.mark.parametrize("lap", [S.SLAQ_LAP_NORMALIZED, S.SLAQ_LAP_COMBINATORIAL])
+@pytest.mark.parametrize("name", ["karate", "dolphins"])
+def test_fig1_graphs(name, lap):
+    header(f"fig1 {name} lap={lap}")
+    csr = load_fig1(name)
+    gpu = gpu_run(csr, 100, 10, 2020, T256, laplacian=lap)
+    ora = oracle_run(csr, 100, 10, 2020, T256, laplacian=lap)
+    assert np.array_equal(gpu["steps"], ora["steps"])
+    assert_signature_parity(gpu, ora, csr.n, name)
+    if lap == S.SLAQ_LAP_COMBINATORIAL:
+        printed = {"karate": 3.154, "dolphins": 3.846}[name]
+        assert abs(gpu["vnge"] - printed) / printed < 1e-2
+
+
+def star_with_isolated(n_leaves, n_iso):
+    s = inputs.star(n_leaves + 1)
+    rp = np.r_[s.row_ptr, np.full(n_iso, s.nnz, dtype=np.int64)]
+    return inputs.CSR(n=s.n + n_iso, row_ptr=rp, col_idx=s.col_idx)
+
+
+@pytest.mark.parametrize("case", ["K30", "star2000", "star_iso", "cycle64", "path50", "edgeless", "single"])
+def test_degenerate_graphs(case):
+    # breakdown (K_n: 2 distinct eigenvalues, star: 3), a heavy row (star
+    # centre of degree 1999), isolated nodes, no edges, a single node
+    header(f"degenerate {case}")
+    csr = {
+        "K30": lambda: inputs.complete(30),
+        "star2000": lambda: inputs.star(2000),
+        "star_iso": lambda: star_with_isolated(500, 300),
+        "cycle64": lambda: inputs.cycle(64),
+        "path50": lambda: inputs.path(50),
+        "edgeless": lambda: inputs.CSR(n=7, row_ptr=np.zeros(8, dtype=np.int64), col_idx=np.zeros(0, dtype=np.int32)),
+        "single": lambda: inputs.CSR(n=1, row_ptr=np.zeros(2, dtype=np.int64), col_idx=np.zeros(0, dtype=np.int32)),
+    }[case]()
+    nv, m = 16, 15
+    gpu = gpu_run(csr, nv, m, 5, T256)
+    ora = oracle_run(csr, nv, m, 5, T256)
+    assert np.array_equal(gpu["steps"], ora["steps"]), (gpu["steps"], ora["steps"])
+    assert_signature_parity(gpu, ora, csr.n, case)
+    assert abs(gpu["heat"][0] - csr.n * math.exp(0)) / csr.n < 0.5  # sanity on scale
+
+
+def test_weighted_graph():
+    header("weighted SBM")
+    csr = inputs.sbm(2500, 4, 0.02, 0.001, seed=3)
+    r = np.repeat(np.arange(csr.n), np.diff(csr.row_ptr))
+    c = csr.col_idx.astype(np.int64)
+    lo, hi = np.minimum(r, c), np.maximum(r, c)
+    w = (1.0 + ((lo * 7 + hi * 13) % 10) / 4.0).astype(np.float32)   # symmetric by construction
+    for lap in (S.SLAQ_LAP_NORMALIZED, S.SLAQ_LAP_COMBINATORIAL):
+        gpu = gpu_run(csr, 20, 12, 9, T256, laplacian=lap, weights=w)
+        ora = oracle_run(csr, 20, 12, 9, T256, laplacian=lap, weights=w.astype(np.float64))
+        assert np.array_equal(gpu["steps"], ora["steps"])
+        assert_signature_parity(gpu, ora, csr.n, f"weighted lap={lap}")
+
+
+def test_ritz_against_lapack_on_oracle_tridiagonals():
+    # the eigensolve alone, fed with the oracle's alpha/beta
+    header("ritz on oracle tridiagonals")
+    csr = inputs.chung_lu(2000, 8000, 2.5, seed=2)
+    for m in (5, 15, 40, 64):
+        ora = oracle_run(csr, 33, m, 1, T256[:4])
+        a = torch.from_numpy(ora["alpha"]).cuda()
+        b = torch.from_numpy(ora["beta"]).cuda()
+        s = torch.from_numpy(ora["steps"]).cuda()
+        th, w2 = S.ritz(a, b, s)
+        th, w2 = th.cpu().numpy(), w2.cpu().numpy()
+        for p in range(33):
+            k = ora["steps"][p]
+            np.testing.assert_allclose(np.sort(th[p, :k]), np.sort(ora["theta"][p, :k]), atol=1e-12)
+            assert abs(w2[p].sum() - 1.0) < 1e-12
+            for tt in (0.1, 1.0, 10.0):
+                g1 = np.sum(w2[p] * np.exp(-tt * th[p]))
+                g0 = np.sum(ora["tau2"][p] * np.exp(-tt * ora["theta"][p]))
+                assert abs(g1 - g0) < 1e-12
+
+
+def test_quadrature_alone_on_oracle_nodes():
+    header("signature/vnge on oracle nodes")
+    csr = inputs.chung_lu(1500, 6000, 2.5, seed=6)
+    ora = oracle_run(csr, 25, 15, 3, T256)
+    th = torch.from_numpy(ora["theta"]).cuda()
+    w2 = torch.from_numpy(ora["tau2"]).cuda()
+    tt = torch.from_numpy(T256).cuda()
+    heat = S.signature(th, w2, csr.n, tt, S.SLAQ_SIG_HEAT).cpu().numpy()
+    wave = S.signature(th, w2, csr.n, tt, S.SLAQ_SIG_WAVE).cpu().numpy()
+    np.testing.assert_allclose(heat, ora["heat"], rtol=1e-13)
+    np.testing.assert_allclose(wave, ora["wave"], rtol=0, atol=1e-11 * csr.n)
+    rp, ci = S.to_device(csr)
+    g = S.build_graph(rp, ci)
+    H = S.vnge(g, th, w2).cpu().numpy()[0]
+    assert abs(H - ora["vnge"]) <= 1e-13 * abs(ora["vnge"])
+
+
+def test_deterministic_bitwise():
+    header("determinism")
+    csr = inputs.chung_lu(10_000, 50_000, 2.5, seed=11)
+    r1 = gpu_run(csr, 10, 15, 3, T256[:8])
+    r2 = gpu_run(csr, 10, 15, 3, T256[:8])
+    assert np.array_equal(r1["alpha"], r2["alpha"]) and np.array_equal(r1["beta"], r2["beta"])
+    assert np.array_equal(r1["heat"], r2["heat"])
+
+
+def test_check_flag_reports_bad_input():
+    header("CHECK flag")
+    csr = inputs.erdos_renyi(50, 0.2, seed=1)
+    rp, ci = S.to_device(csr)
+    S.build_graph(rp, ci, check=True)  # valid
+    bad = ci.clone()
+    bad[3] = 10_000
+    with pytest.raises(S.SlaqError) as e:
+        S.build_graph(rp, bad, check=True)
+    assert e.value.status == 7
+    # in the row of a neighbour j of node 0, replace the entry 0 by a node c
+    # that j does not touch: (j,c) and (0,j) lose their mirrors
+    col = csr.col_idx.copy()
+    j = int(col[csr.row_ptr[1] - 1])
+    rj = slice(csr.row_ptr[j], csr.row_ptr[j + 1])
+    seg = col[rj].copy()
+    c = max(set(range(50)) - set(seg.tolist()) - {j})
+    seg[np.flatnonzero(seg == 0)[0]] = c
+    seg.sort()
+    col[rj] = seg
+    with pytest.raises(S.SlaqError) as e:
+        S.build_graph(rp, torch.from_numpy(col).cuda(), check=True)
+    assert e.value.status == 2
+    w = torch.ones(csr.nnz, dtype=torch.float32, device="cuda")
+    w[5] = -1.0
+    with pytest.raises(S.SlaqError) as e:
+        S.build_graph(rp, ci, w, check=True)
+    assert e.value.status in (2, 3)
+
+
+def test_argument_errors_before_launch():
+    header("host argument errors")
+    csr = inputs.cycle(10)
+    rp, ci = S.to_device(csr)
+    g = S.build_graph(rp, ci)
+    for nv, m in ((0, 5), (5000, 5), (4, 0), (4, 65)):
+        with pytest.raises(S.SlaqError) as e:
+            S.lanczos(g, nv, m, 1, workspace=torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
+        assert e.value.status == 1
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.SlaqError) as e:
+        S.lanczos(g, 4, 5, 1, workspace=small)
+    assert e.value.status == 4
