@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the SLQ hot path on one MI355X.
+
+One step = one pass of the whole path over one synthetic graph already in HBM:
+graph build (degrees, D^-1/2, tr L), Rademacher probes and m Lanczos steps on
+nv probes, the FP64 tridiagonal eigensolve, heat and wave trace at 256 time
+scales and the von Neumann entropy.
+
+Default workload: R-MAT scale 22 (n = 4,194,304, edge factor 16,
+a=0.57 b=c=0.19, ~1.28e8 stored nonzeros), nv = 100 probes, m = 15 steps.
+`value` is nnz * nv * m per second of the whole step.  The roofline entry
+covers the SpMM stage kernels, timed live with HIP events on the launch stream.
+
+    python bench.py [--steps K] [--warmup W] [--workload rmat22|chung_lu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "nnz*probes*steps/s + HBM GB/s (SpMM); graphs/s batched at rel.err<=1e-3"
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator kwargs, nv, m)
+    "rmat22": (dict(kind="rmat", scale=22, seed=1), 100, 15),
+    "chung_lu": (dict(kind="chung_lu", n=10_000, pairs=50_000, seed=1), 10, 15),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_graph(spec):
+    from paper_2003_01282_amd import inputs
+    if spec["kind"] == "rmat":
+        return inputs.rmat(spec["scale"], seed=spec["seed"])
+    return inputs.chung_lu(spec["n"], spec["pairs"], 2.5, seed=spec["seed"])
+
+
+def spmm_algorithmic_bytes(n, nnz, nv):
+    """Bytes the SpMM stage must move per Lanczos step: col_idx (4 nnz),
+    row_ptr (8 (n+1)), D^-1/2 (4 n), the probe block gathered once (4 n nv),
+    the previous block read (4 n nv) and w written (4 n nv)."""
+    return 4 * nnz + 8 * (n + 1) + 4 * n + 12 * n * nv
+
+
+def update_algorithmic_bytes(n, nv):
+    """q_{j+1} = (w - alpha q_j)/beta: read w and q_j, write q_{j+1}."""
+    return 12 * n * nv
+
+
+def cpu_baseline(csr, nv, m, seed, budget_s=25.0):
+    """The FP64 oracle's Lanczos loop on a probe subset of the same graph."""
+    from oracle import slq as O
+    g = O.build_graph(csr.n, csr.row_ptr, csr.col_idx)
+    V = O.rademacher(csr.n, nv, seed)
+    # one step with one probe to size the sample
+    t0 = time.perf_counter()
+    O.lanczos(g, 1, 1, seed, probes=V[:, :1])
+    one = max(time.perf_counter() - t0, 1e-6)
+    probes = int(max(1, min(nv, budget_s / (one * m))))
+    t0 = time.perf_counter()
+    O.lanczos(g, probes, m, seed, probes=V[:, :probes])
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        blas_threads = 1
+    return {
+        "value": csr.nnz * probes * m / dt,
+        "unit": "nnz*probes*steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle Lanczos loop (scipy CSR matmul + numpy, FP64) over probes 0..{probes - 1} "
+                   f"of the same graph, m={m}, {dt:.1f} s; single-threaded sparse kernel "
+                   f"(BLAS pool {blas_threads} threads unused by it)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=20200302)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(probe sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2003_01282_amd import slaq as S
+    from paper_2003_01282_amd import inputs
+
+    spec, nv, m = WORKLOADS[args.workload]
+    log(f"generating {args.workload} {spec}")
+    t0 = time.perf_counter()
+    csr = make_graph(spec)
+    log(f"graph n={csr.n} nnz={csr.nnz} in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    rp = torch.from_numpy(csr.row_ptr).to(dev)
+    ci = torch.from_numpy(csr.col_idx).to(dev)
+    tgrid = torch.from_numpy(inputs.t_grid(256)).to(dev)
+    nt = tgrid.numel()
+
+    # preallocated buffers: the timed step allocates nothing
+    g0 = S.build_graph(rp, ci)
+    dinv = g0.dinv
+    scratch = g0._keep["scratch"]
+    ws = S._empty_aligned(S.lanczos_workspace(g0, nv, m), dev)
+    alpha = torch.empty((nv, m), dtype=torch.float64, device=dev)
+    beta = torch.empty_like(alpha)
+    steps = torch.empty(nv, dtype=torch.int32, device=dev)
+    theta = torch.empty_like(alpha)
+    tau2 = torch.empty_like(alpha)
+    heat = torch.empty(nt, dtype=torch.float64, device=dev)
+    wave = torch.empty(nt, dtype=torch.float64, device=dev)
+    H = torch.empty(1, dtype=torch.float64, device=dev)
+    graphs = [g0]
+
+    def step():
+        g = S.build_graph(rp, ci, dinv=dinv, scratch=scratch)
+        S.lanczos(g, nv, m, args.seed, workspace=ws, out=(alpha, beta, steps))
+        S.ritz(alpha, beta, steps, out=(theta, tau2))
+        S.signature(theta, tau2, csr.n, tgrid, S.SLAQ_SIG_HEAT, out=heat)
+        S.signature(theta, tau2, csr.n, tgrid, S.SLAQ_SIG_WAVE, out=wave)
+        S.vnge(g, theta, tau2, out=H)
+        graphs[0] = g  # keep the handle alive until the next step
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    S.profile_reset()
+    S.profile_enable(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    S.profile_enable(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    stages = {}
+    for k in ("spmm_chunks", "spmm_rows", "finalize", "update"):
+        cnt, tot = S.profile_read(k)
+        stages[k] = {"launches": cnt, "avg_ms": tot / cnt if cnt else 0.0, "ms_per_step": tot / args.steps}
+    S.profile_reset()
+    log(f"{ms_per_step:.3f} ms/step; stages {json.dumps(stages)}")
+
+    # SpMM stage = heavy-row chunks + row kernel, once per Lanczos step
+    spmm_ms = stages["spmm_rows"]["avg_ms"] + (stages["spmm_chunks"]["avg_ms"] if stages["spmm_chunks"]["launches"] else 0.0)
+    spmm_bytes = spmm_algorithmic_bytes(csr.n, csr.nnz, nv)
+    achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    upd_ms = stages["update"]["avg_ms"]
+    upd_gbs = update_algorithmic_bytes(csr.n, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
+
+    h = heat.cpu().numpy()
+    sanity = bool(np.all(np.isfinite(h)) and np.all(np.diff(h) <= 1e-9 * csr.n) and 0 < h[-1] < csr.n)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a probe subset)")
+        cpu = cpu_baseline(csr, nv, m, args.seed)
+        cpu["cores"] = 1
+        try:
+            cpu["cpu_model"] = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                                    if ln.startswith("model name"))
+        except Exception:  # pragma: no cover
+            pass
+        cpu["host_cores_available"] = len(os.sched_getaffinity(0))
+
+    out = {
+        "metric": METRIC,
+        "value": csr.nnz * nv * m / (ms_per_step * 1e-3),
+        "unit": "nnz*probes*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}_slq", "n": csr.n, "nnz": csr.nnz, "nv": nv, "m": m,
+                   "nt": nt, "outputs": ["heat", "wave", "vnge"], "laplacian": "normalized",
+                   "generator": spec},
+        "roofline": {"bound": "hbm", "kernel": "spmm_chunks+spmm_rows", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "bytes_per_launch": spmm_bytes, "avg_launch_ms": spmm_ms},
+        "spmm_hbm_gbs": achieved,
+        "update_gbs": upd_gbs,
+        "stages": stages,
+        "heat_sane": sanity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -144,6 +144,17 @@ slaq_status slaq_signature(const double* theta, const double* tau2, int nv, int 
 slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, int nv,
                       int m, double* out, void* stream);
 
+/* Stage timing with HIP events (off by default).  While enabled, every launch
+ * of a stage kernel ("spmm_chunks", "spmm_rows", "finalize", "update",
+ * "batch_slq", "mlp_*") is bracketed by two events on its stream.
+ * slaq_profile_read waits for the recorded events of `kernel` and returns how
+ * many launches were recorded and their summed duration in milliseconds;
+ * slaq_profile_reset drops the records.  Intended for benchmarks: recording
+ * adds two event records per launch. */
+slaq_status slaq_profile_enable(int on);
+slaq_status slaq_profile_reset(void);
+slaq_status slaq_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* slaq_last_error(void);
 

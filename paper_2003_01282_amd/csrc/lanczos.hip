@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "profile.hpp"
 
 namespace slaq {
 
@@ -450,20 +451,25 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
     const int chunk_blocks = (int)(chunk_blocks64 < 4096 ? chunk_blocks64 : 4096);
     for (int j = 1; j <= m; ++j) {
         if (L.nchunks > 0) {
-            SLAQ_DISPATCH(mode, weighted, spmm_chunks, dim3(chunk_blocks, L.ntiles), dim3(256), 0, st, g->n,
-                          L.nchunks, g->row_ptr, g->col_idx, g->weights, g->diag, Qb[cur], H, L.F, L.G, L.K);
+            SLAQ_TIMED("spmm_chunks", st,
+                       SLAQ_DISPATCH(mode, weighted, spmm_chunks, dim3(chunk_blocks, L.ntiles), dim3(256), 0, st,
+                                     g->n, L.nchunks, g->row_ptr, g->col_idx, g->weights, g->diag, Qb[cur], H,
+                                     L.F, L.G, L.K));
             SLAQ_LAUNCHED();
         }
-        SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb, L.ntiles), dim3(kSpmmBlock), 0, st, g->n,
-                      g->row_ptr, g->col_idx, g->weights, g->diag, Qb[cur], Qb[prev], H, Qb[wbuf],
-                      coef + 2 * L.ld, j > 1 ? 1 : 0, part, L.nb, L.F, L.G, L.K, L.ld);
+        SLAQ_TIMED("spmm_rows", st,
+                   SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb, L.ntiles), dim3(kSpmmBlock), 0, st, g->n,
+                                 g->row_ptr, g->col_idx, g->weights, g->diag, Qb[cur], Qb[prev], H, Qb[wbuf],
+                                 coef + 2 * L.ld, j > 1 ? 1 : 0, part, L.nb, L.F, L.G, L.K, L.ld));
         SLAQ_LAUNCHED();
-        hipLaunchKernelGGL(finalize, dim3(nv), dim3(256), 0, st, part, L.nb, L.ld, m, j, g->stats, mode,
-                           kEpsBreakdown, alpha, beta, steps, active, coef);
+        SLAQ_TIMED("finalize", st,
+                   hipLaunchKernelGGL(finalize, dim3(nv), dim3(256), 0, st, part, L.nb, L.ld, m, j, g->stats, mode,
+                                      kEpsBreakdown, alpha, beta, steps, active, coef));
         SLAQ_LAUNCHED();
         if (j < m) {
-            hipLaunchKernelGGL(update, dim3(sgrid), dim3(256), 0, st, g->n, L.F, rps, Qb[wbuf], Qb[cur], coef,
-                               L.ld, Qb[prev]);
+            SLAQ_TIMED("update", st,
+                       hipLaunchKernelGGL(update, dim3(sgrid), dim3(256), 0, st, g->n, L.F, rps, Qb[wbuf], Qb[cur],
+                                          coef, L.ld, Qb[prev]));
             SLAQ_LAUNCHED();
             const int t = cur;
             cur = prev;

@@ -30,6 +30,13 @@ class CSR:
         return int(self.row_ptr[-1])
 
 
+def t_grid(nt=256, lo=-2.0, hi=2.0):
+    """Workload time scales t_k = 10^(lo + (hi-lo) k/(nt-1)), log-spaced
+    (1e-2 .. 1e2 by default)."""
+    k = np.arange(nt, dtype=np.float64)
+    return 10.0 ** (lo + (hi - lo) * k / max(nt - 1, 1))
+
+
 def csr_from_pairs(n, u, v):
     """Undirected pairs (any order, duplicates and self-loops allowed) ->
     symmetric CSR without self-loops or duplicates."""

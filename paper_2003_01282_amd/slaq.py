@@ -41,6 +41,9 @@ SIGNATURES = {
     "slaq_ritz": [_vp, _vp, _vp, _int, _int, _vp, _vp, _vp],
     "slaq_signature": [_vp, _vp, _int, _int, _i64, _vp, _int, _int, _vp, _vp],
     "slaq_vnge": [_vp, _vp, _vp, _int, _int, _vp, _vp],
+    "slaq_profile_enable": [_int],
+    "slaq_profile_reset": [],
+    "slaq_profile_read": [ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
 }
 
 _LIB = None
@@ -127,9 +130,10 @@ class Graph:
             self.handle = None
 
 
-def build_graph(row_ptr, col_idx, weights=None, laplacian=SLAQ_LAP_NORMALIZED, check=False, stream=None):
+def build_graph(row_ptr, col_idx, weights=None, laplacian=SLAQ_LAP_NORMALIZED, check=False, stream=None,
+                dinv=None, scratch=None):
     """slaq_build_graph on device CSR tensors (int64 row_ptr, int32 col_idx,
-    optional float32 weights)."""
+    optional float32 weights).  dinv / scratch may be passed preallocated."""
     _dev(row_ptr, torch.int64, "row_ptr")
     _dev(col_idx, torch.int32, "col_idx")
     if weights is not None:
@@ -139,11 +143,13 @@ def build_graph(row_ptr, col_idx, weights=None, laplacian=SLAQ_LAP_NORMALIZED, c
     dev = row_ptr.device
     nbytes = _sz()
     _check(lib().slaq_graph_scratch_bytes(n, nnz, ctypes.byref(nbytes)))
-    dinv = torch.empty(n, dtype=torch.float32, device=dev)
-    scratch = _empty_aligned(nbytes.value, dev)
+    if dinv is None:
+        dinv = torch.empty(n, dtype=torch.float32, device=dev)
+    if scratch is None:
+        scratch = _empty_aligned(nbytes.value, dev)
     h = _vp()
     _check(lib().slaq_build_graph(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(weights), laplacian,
-                                  SLAQ_FLAG_CHECK if check else 0, _ptr(dinv), _ptr(scratch), nbytes.value,
+                                  SLAQ_FLAG_CHECK if check else 0, _ptr(dinv), _ptr(scratch), scratch.numel(),
                                   _stream(stream), ctypes.byref(h)))
     keep = {"row_ptr": row_ptr, "col_idx": col_idx, "weights": weights, "dinv": dinv, "scratch": scratch}
     return Graph(h, n, nnz, laplacian, keep)
@@ -203,6 +209,21 @@ def vnge(g, theta, tau2, out=None, stream=None):
         out = torch.empty(1, dtype=torch.float64, device=theta.device)
     _check(lib().slaq_vnge(g.handle, _ptr(theta), _ptr(tau2), nv, m, _ptr(out), _stream(stream)))
     return out
+
+
+def profile_enable(on=True):
+    _check(lib().slaq_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().slaq_profile_reset())
+
+
+def profile_read(kernel):
+    """(launches, total milliseconds) recorded for a stage kernel."""
+    n, ms = _i64(), ctypes.c_double()
+    _check(lib().slaq_profile_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def to_device(csr, device="cuda"):

@@ -88,9 +88,19 @@ def test_degenerate_graphs(case):
     nv, m = 16, 15
     gpu = gpu_run(csr, nv, m, 5, T256)
     ora = oracle_run(csr, nv, m, 5, T256)
-    assert np.array_equal(gpu["steps"], ora["steps"]), (gpu["steps"], ora["steps"])
+    # After an exact breakdown the FP32 residual is rounding noise amplified by
+    # 1/beta of earlier steps (about sqrt(n/2) on a star), so the GPU may carry
+    # on past the FP64 stopping step into directions whose Gauss weights are
+    # O(noise^2).  Coefficients are compared up to the shorter run, the
+    # signatures in full.
+    for p in range(nv):
+        k = int(min(gpu["steps"][p], ora["steps"][p]))
+        np.testing.assert_allclose(gpu["alpha"][p, :k], ora["alpha"][p, :k], rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(gpu["beta"][p, :k - 1], ora["beta"][p, :k - 1], rtol=1e-5, atol=1e-5)
+        if gpu["steps"][p] > ora["steps"][p]:
+            assert gpu["beta"][p, k - 1] < 1e-4
     assert_signature_parity(gpu, ora, csr.n, case)
-    assert abs(gpu["heat"][0] - csr.n * math.exp(0)) / csr.n < 0.5  # sanity on scale
+    np.testing.assert_allclose(gpu["tau2"].sum(axis=1), 1.0, atol=1e-9)
 
 
 def test_weighted_graph():
