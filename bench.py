@@ -42,16 +42,19 @@ def make_graph(spec):
     return inputs.chung_lu(spec["n"], spec["pairs"], 2.5, seed=spec["seed"])
 
 
-def spmm_algorithmic_bytes(n, nnz, nv):
+def spmm_algorithmic_bytes(n, n_act, nnz, nv):
     """Bytes the SpMM stage must move per Lanczos step: col_idx (4 nnz),
-    row_ptr (8 (n+1)), D^-1/2 (4 n), the probe block gathered once (4 n nv),
-    the previous block read (4 n nv) and w written (4 n nv)."""
-    return 4 * nnz + 8 * (n + 1) + 4 * n + 12 * n * nv
+    row_ptr (8 (n+1)), D^-1/2 (4 n), and per non-isolated node and probe the
+    block gathered once (4), the previous block read (4) and w written (4).
+    Isolated nodes carry no vector data (their components are one FP64 scalar
+    per probe), so only the n_act non-isolated rows count."""
+    return 4 * nnz + 8 * (n + 1) + 4 * n + 12 * n_act * nv
 
 
-def update_algorithmic_bytes(n, nv):
-    """q_{j+1} = (w - alpha q_j)/beta: read w and q_j, write q_{j+1}."""
-    return 12 * n * nv
+def update_algorithmic_bytes(n, n_act, nv):
+    """R_{j+1} = w - a R_j: read w and R_j, write R_{j+1} on the n_act
+    non-isolated rows, plus D (4 n) to skip isolated rows."""
+    return 4 * n + 12 * n_act * nv
 
 
 def cpu_baseline(csr, nv, m, seed, budget_s=25.0):
@@ -153,18 +156,19 @@ def main():
     S.profile_enable(False)
     ms_per_step = 1e3 * elapsed / args.steps
     stages = {}
-    for k in ("spmm_chunks", "spmm_rows", "finalize", "update"):
+    for k in ("spmm_pieces", "spmm_rows", "finalize", "update"):
         cnt, tot = S.profile_read(k)
         stages[k] = {"launches": cnt, "avg_ms": tot / cnt if cnt else 0.0, "ms_per_step": tot / args.steps}
     S.profile_reset()
     log(f"{ms_per_step:.3f} ms/step; stages {json.dumps(stages)}")
 
     # SpMM stage = heavy-row chunks + row kernel, once per Lanczos step
-    spmm_ms = stages["spmm_rows"]["avg_ms"] + (stages["spmm_chunks"]["avg_ms"] if stages["spmm_chunks"]["launches"] else 0.0)
-    spmm_bytes = spmm_algorithmic_bytes(csr.n, csr.nnz, nv)
+    spmm_ms = stages["spmm_rows"]["avg_ms"] + (stages["spmm_pieces"]["avg_ms"] if stages["spmm_pieces"]["launches"] else 0.0)
+    n_act = csr.n - int(np.count_nonzero(np.diff(csr.row_ptr) == 0))
+    spmm_bytes = spmm_algorithmic_bytes(csr.n, n_act, csr.nnz, nv)
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
     upd_ms = stages["update"]["avg_ms"]
-    upd_gbs = update_algorithmic_bytes(csr.n, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
+    upd_gbs = update_algorithmic_bytes(csr.n, n_act, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
 
     h = heat.cpu().numpy()
     sanity = bool(np.all(np.isfinite(h)) and np.all(np.diff(h) <= 1e-9 * csr.n) and 0 < h[-1] < csr.n)
@@ -196,8 +200,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}_slq", "n": csr.n, "nnz": csr.nnz, "nv": nv, "m": m,
                    "nt": nt, "outputs": ["heat", "wave", "vnge"], "laplacian": "normalized",
-                   "generator": spec},
-        "roofline": {"bound": "hbm", "kernel": "spmm_chunks+spmm_rows", "achieved": achieved,
+                   "generator": spec, "n_nonisolated": n_act, "schedule": graphs[0].schedule()},
+        "roofline": {"bound": "hbm", "kernel": "spmm_pieces+spmm_rows", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "bytes_per_launch": spmm_bytes, "avg_launch_ms": spmm_ms},
         "spmm_hbm_gbs": achieved,

@@ -96,6 +96,17 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr,
 slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* trace,
                             int64_t* n_isolated, double* max_degree);
 
+/* Row schedule of the SpMM.  Rows with at least heavy_min nonzeros are cut
+ * into pieces of at most `piece` nonzeros that separate waves reduce in
+ * parallel (defaults 256 and 512; heavy_min >= 32, piece a multiple of 64 and
+ * >= 64).  Setting it rebuilds the piece plan on `stream`; query
+ * slaq_lanczos_workspace again afterwards, its size depends on the schedule.
+ * slaq_graph_schedule reports the schedule and (waiting for the stream of the
+ * build) the number of heavy rows and pieces; any pointer may be NULL. */
+slaq_status slaq_graph_set_schedule(slaq_graph_t g, int heavy_min, int piece, void* stream);
+slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int64_t* n_heavy,
+                                int64_t* n_pieces);
+
 /* Frees the host handle (never caller memory). */
 slaq_status slaq_graph_destroy(slaq_graph_t g);
 
@@ -118,7 +129,9 @@ slaq_status slaq_lanczos_workspace(slaq_graph_t g, int nv, int m, size_t* bytes)
  *                i.e. 2 or 2 max D_ii); entries past steps[p] are 0.  This is
  *                not an error.
  * workspace: device memory of slaq_lanczos_workspace() bytes; 1 <= nv <=
- * SLAQ_MAX_PROBES, 1 <= m <= SLAQ_MAX_STEPS. */
+ * SLAQ_MAX_PROBES, 1 <= m <= SLAQ_MAX_STEPS.  Isolated nodes (zero rows of L)
+ * are not stored in the workspace: on them every Lanczos vector is a multiple
+ * of the probe, carried as an FP64 scalar per probe. */
 slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha,
                          double* beta, int32_t* steps, void* workspace,
                          size_t workspace_bytes, void* stream);

@@ -33,7 +33,7 @@ void clear_error();
         }                                                                           \
     } while (0)
 
-// launch-error check right after a <<<>>> launch
+// launch-error check right after a launch
 #define SLAQ_LAUNCHED() SLAQ_HIP(hipGetLastError())
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -45,11 +45,14 @@ struct GraphStats {
     double max_degree;     // max_i D_ii
     double sum_degree;     // sum_i D_ii
     long long n_isolated;  // #{i : D_ii = 0}
+    long long n_heavy;     // rows split into pieces (degree >= heavy_min)
+    long long n_pieces;    // total pieces of the heavy rows
     unsigned int check;    // SLAQ_FLAG_CHECK findings (bit mask, see graph.hip)
     unsigned int pad;
 };
 
 constexpr int kBuildBlocks = 1024;  // grid of the degree kernel (partials size)
+constexpr int kPlanBlock = 256;     // rows per block of the plan kernels
 
 struct BuildPartial {
     double max_degree;
@@ -57,6 +60,14 @@ struct BuildPartial {
     long long nonisolated;
     long long pad;
 };
+
+// Row schedule of the SpMM: rows of degree >= heavy_min are cut into pieces of
+// at most `piece` nonzeros (a piece never crosses a row).  heavy_min and piece
+// are tunable (slaq_graph_set_schedule); these are the defaults and bounds.
+constexpr int kDefaultHeavyMin = 256;
+constexpr int kDefaultPiece = 512;
+constexpr int kMinHeavyMin = 32;
+constexpr int kMinPiece = 64;
 
 }  // namespace slaq
 
@@ -67,24 +78,31 @@ struct slaq_graph_s {
     const int32_t* col_idx;
     const float* weights;   // NULL = unweighted
     int laplacian;          // SLAQ_LAP_*
-    float* diag;            // dinv (normalized) or degree (combinatorial)
+    float* diag;            // dinv (normalized) or degree (combinatorial); 0 <=> isolated
     slaq::GraphStats* stats;
     slaq::BuildPartial* partials;
-    hipStream_t stream;     // stream of the build (slaq_graph_info waits on it)
+    long long* blockcounts;  // [nplan] heavy rows, pieces per plan block, then offsets
+    int32_t* hrow;           // heavy row ids, increasing
+    int64_t* hoff;           // first piece of each heavy row, hoff[n_heavy] = n_pieces
+    int64_t max_heavy;       // capacity of hrow / hoff
+    int heavy_min;
+    int piece;
+    hipStream_t stream;      // stream of the build (slaq_graph_info waits on it)
 };
 
 namespace slaq {
 
+// Builds (or rebuilds) the heavy-row plan of g on `st` with its heavy_min/piece.
+slaq_status build_plan(slaq_graph_s* g, hipStream_t st);
+
 // ------------------------------------------------------- Lanczos layout ----
-// Probe block row-major [n][ld], ld = nv rounded up to a multiple of 4 floats,
-// so one node's probes are ld/4 float4 words.  Rows of degree >= kHeavyMin are
-// split into aligned chunks of kChunk nonzeros whose partial products are
-// computed by a separate kernel (bounded work per wave).
-constexpr int kChunk = 128;
-constexpr int kHeavyMin = 2 * kChunk;
+// Vector blocks are row-major [n][ld], ld = nv rounded up to a multiple of 4
+// floats, so one node's probes are ld/4 float4 words ("quads").  A wave splits
+// into K = 64/G groups of G = min(ld/4, 64) lanes; one group covers one node's
+// quads of a probe tile (64 quads = 256 probes).
+constexpr int kQuadsPerTile = 64;
 constexpr int kSpmmBlock = 256;       // 4 waves
-constexpr int kSpmmMaxBlocks = 2048;  // persistent grid of the SpMM kernel
-constexpr int kQuadsPerTile = 64;     // float4 words per probe tile (256 probes)
+constexpr int kRowsPerWindow = 64;    // rows a wave takes per window
 
 inline int lanczos_ld(int nv) { return (nv + 3) / 4 * 4; }
 

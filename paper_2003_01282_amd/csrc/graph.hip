@@ -159,6 +159,160 @@ __global__ void __launch_bounds__(256) check_kernel(int64_t n, int64_t nnz,
     if (bad) atomicOr(&st->check, bad);
 }
 
+
+// ------------------------------------------------------------ row plan ----
+// Heavy rows (degree >= heavy_min) are listed in increasing id order with the
+// offset of their first piece (ceil(degree / piece) pieces each).  Three
+// kernels: per-block counts, one-block exclusive scan, per-block writes, so
+// the list is deterministic.
+__global__ void __launch_bounds__(kPlanBlock) plan_count(int64_t n, const int64_t* __restrict__ rp,
+                                                         int heavy_min, int piece,
+                                                         long long* __restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * kPlanBlock + threadIdx.x;
+    long long h = 0, p = 0;
+    if (i < n) {
+        const int64_t d = rp[i + 1] - rp[i];
+        if (d >= heavy_min) {
+            h = 1;
+            p = (d + piece - 1) / piece;
+        }
+    }
+    __shared__ long long sh[kPlanBlock], sp[kPlanBlock];
+    sh[threadIdx.x] = h;
+    sp[threadIdx.x] = p;
+    __syncthreads();
+    for (int off = kPlanBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sh[threadIdx.x] += sh[threadIdx.x + off];
+            sp[threadIdx.x] += sp[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[2 * (int64_t)blockIdx.x] = sh[0];
+        counts[2 * (int64_t)blockIdx.x + 1] = sp[0];
+    }
+}
+
+// One block: exclusive scan of the per-block counts into offs (same layout).
+__global__ void __launch_bounds__(1024) plan_scan(int64_t nblocks, const long long* __restrict__ counts,
+                                                  long long* __restrict__ offs, GraphStats* __restrict__ st,
+                                                  int64_t* __restrict__ hoff) {
+    const int t = threadIdx.x;
+    const int64_t per = (nblocks + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    long long h = 0, p = 0;
+    for (int64_t b = b0; b < b1; ++b) {
+        h += counts[2 * b];
+        p += counts[2 * b + 1];
+    }
+    __shared__ long long sh[1024], sp[1024];
+    sh[t] = h;
+    sp[t] = p;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over the 1024 thread sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        long long ah = 0, ap = 0;
+        if (t >= off) {
+            ah = sh[t - off];
+            ap = sp[t - off];
+        }
+        __syncthreads();
+        sh[t] += ah;
+        sp[t] += ap;
+        __syncthreads();
+    }
+    long long run_h = t > 0 ? sh[t - 1] : 0, run_p = t > 0 ? sp[t - 1] : 0;
+    for (int64_t b = b0; b < b1; ++b) {
+        offs[2 * b] = run_h;
+        offs[2 * b + 1] = run_p;
+        run_h += counts[2 * b];
+        run_p += counts[2 * b + 1];
+    }
+    if (t == 1023) {
+        st->n_heavy = sh[1023];
+        st->n_pieces = sp[1023];
+        hoff[sh[1023]] = sp[1023];
+    }
+}
+
+__global__ void __launch_bounds__(kPlanBlock) plan_write(int64_t n, const int64_t* __restrict__ rp,
+                                                         int heavy_min, int piece,
+                                                         const long long* __restrict__ offs,
+                                                         int32_t* __restrict__ hrow, int64_t* __restrict__ hoff) {
+    const int64_t i = (int64_t)blockIdx.x * kPlanBlock + threadIdx.x;
+    long long h = 0, p = 0;
+    if (i < n) {
+        const int64_t d = rp[i + 1] - rp[i];
+        if (d >= heavy_min) {
+            h = 1;
+            p = (d + piece - 1) / piece;
+        }
+    }
+    __shared__ long long sh[kPlanBlock], sp[kPlanBlock];
+    const int t = threadIdx.x;
+    sh[t] = h;
+    sp[t] = p;
+    __syncthreads();
+    for (int off = 1; off < kPlanBlock; off <<= 1) {
+        long long ah = 0, ap = 0;
+        if (t >= off) {
+            ah = sh[t - off];
+            ap = sp[t - off];
+        }
+        __syncthreads();
+        sh[t] += ah;
+        sp[t] += ap;
+        __syncthreads();
+    }
+    if (h) {
+        const long long oh = offs[2 * (int64_t)blockIdx.x] + sh[t] - 1;
+        const long long op = offs[2 * (int64_t)blockIdx.x + 1] + sp[t] - p;
+        hrow[oh] = (int32_t)i;
+        hoff[oh] = op;
+    }
+}
+
+struct ScratchLayout {
+    size_t off_stats, off_part, off_counts, off_hrow, off_hoff, total;
+    int64_t nplan, max_heavy;
+};
+
+static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
+    ScratchLayout L{};
+    L.nplan = (n + kPlanBlock - 1) / kPlanBlock;
+    L.max_heavy = nnz / kMinHeavyMin;
+    if (L.max_heavy > n) L.max_heavy = n;
+    size_t off = 0;
+    L.off_stats = off;
+    off += align_up(sizeof(GraphStats), 256);
+    L.off_part = off;
+    off += align_up(sizeof(BuildPartial) * kBuildBlocks, 256);
+    L.off_counts = off;
+    off += align_up(sizeof(long long) * 4 * (size_t)L.nplan, 256);
+    L.off_hrow = off;
+    off += align_up(sizeof(int32_t) * (size_t)(L.max_heavy + 1), 256);
+    L.off_hoff = off;
+    off += align_up(sizeof(int64_t) * (size_t)(L.max_heavy + 1), 256);
+    L.total = off;
+    return L;
+}
+
+slaq_status build_plan(slaq_graph_s* g, hipStream_t st) {
+    const int64_t nplan = (g->n + kPlanBlock - 1) / kPlanBlock;
+    long long* counts = g->blockcounts;
+    long long* offs = g->blockcounts + 2 * nplan;
+    hipLaunchKernelGGL(plan_count, dim3((unsigned)nplan), dim3(kPlanBlock), 0, st, g->n, g->row_ptr,
+                       g->heavy_min, g->piece, counts);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(plan_scan, dim3(1), dim3(1024), 0, st, nplan, counts, offs, g->stats, g->hoff);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(plan_write, dim3((unsigned)nplan), dim3(kPlanBlock), 0, st, g->n, g->row_ptr,
+                       g->heavy_min, g->piece, offs, g->hrow, g->hoff);
+    SLAQ_LAUNCHED();
+    return SLAQ_OK;
+}
+
 }  // namespace slaq
 
 using namespace slaq;
@@ -170,7 +324,7 @@ const char* slaq_last_error(void) { return g_err; }
 slaq_status slaq_graph_scratch_bytes(int64_t n, int64_t nnz, size_t* bytes) {
     SLAQ_REQUIRE(bytes, SLAQ_ERR_INVALID_ARG, "bytes is NULL");
     SLAQ_REQUIRE(n > 0 && nnz >= 0, SLAQ_ERR_INVALID_ARG, "need n > 0 and nnz >= 0");
-    *bytes = align_up(sizeof(GraphStats), 256) + align_up(sizeof(BuildPartial) * kBuildBlocks, 256);
+    *bytes = scratch_layout(n, nnz).total;
     return SLAQ_OK;
 }
 
@@ -197,8 +351,9 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
 
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)scratch;
-    GraphStats* stats = (GraphStats*)base;
-    BuildPartial* part = (BuildPartial*)(base + align_up(sizeof(GraphStats), 256));
+    const ScratchLayout SL = scratch_layout(n, nnz);
+    GraphStats* stats = (GraphStats*)(base + SL.off_stats);
+    BuildPartial* part = (BuildPartial*)(base + SL.off_part);
 
     int blocks = (int)((n + 255) / 256);
     if (blocks > kBuildBlocks) blocks = kBuildBlocks;
@@ -232,6 +387,13 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
 
     slaq_graph_s* g = new (std::nothrow) slaq_graph_s;
     SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "out of host memory");
+    g->blockcounts = (long long*)(base + SL.off_counts);
+    g->hrow = (int32_t*)(base + SL.off_hrow);
+    g->hoff = (int64_t*)(base + SL.off_hoff);
+    g->max_heavy = SL.max_heavy;
+    g->heavy_min = kDefaultHeavyMin;
+    g->piece = kDefaultPiece;
+    g->row_ptr = row_ptr;
     g->n = n;
     g->nnz = nnz;
     g->row_ptr = row_ptr;
@@ -242,6 +404,11 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->stats = stats;
     g->partials = part;
     g->stream = st;
+    const slaq_status ps = build_plan(g, st);
+    if (ps != SLAQ_OK) {
+        delete g;
+        return ps;
+    }
     *out = g;
     return SLAQ_OK;
 }
@@ -258,6 +425,33 @@ slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* tr
     if (trace) *trace = hs.trace;
     if (n_isolated) *n_isolated = hs.n_isolated;
     if (max_degree) *max_degree = hs.max_degree;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_set_schedule(slaq_graph_t g, int heavy_min, int piece, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    SLAQ_REQUIRE(heavy_min >= kMinHeavyMin, SLAQ_ERR_INVALID_ARG, "heavy_min must be >= %d", kMinHeavyMin);
+    SLAQ_REQUIRE(piece >= kMinPiece && piece % 64 == 0, SLAQ_ERR_INVALID_ARG,
+                 "piece must be a multiple of 64 and >= %d", kMinPiece);
+    g->heavy_min = heavy_min;
+    g->piece = piece;
+    return build_plan(g, (hipStream_t)stream);
+}
+
+slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int64_t* n_heavy,
+                                int64_t* n_pieces) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    if (heavy_min) *heavy_min = g->heavy_min;
+    if (piece) *piece = g->piece;
+    if (n_heavy || n_pieces) {
+        GraphStats hs;
+        SLAQ_HIP(hipMemcpyAsync(&hs, g->stats, sizeof(hs), hipMemcpyDeviceToHost, g->stream));
+        SLAQ_HIP(hipStreamSynchronize(g->stream));
+        if (n_heavy) *n_heavy = hs.n_heavy;
+        if (n_pieces) *n_pieces = hs.n_pieces;
+    }
     return SLAQ_OK;
 }
 

@@ -2,16 +2,23 @@
 // three-term recurrence on nv probes at once (paper §3.1, "s-step Lanczos";
 // Algorithm 1's lanczos(L, s, nv)).
 //
-// Per step j the work is
-//   spmm_chunks  partial A-products of aligned kChunk-nonzero chunks of heavy rows
-//   spmm_rows    w = L q_j - beta_{j-1} q_{j-1} for every row (FP32), and per
-//                probe the FP64 partial sums q.w, w.w, q.q of this block
-//   finalize     fixed-order sum of the partials: alpha_j = q.w,
-//                beta_j^2 = w.w - 2 alpha q.w + alpha^2 q.q (= ||w - alpha q||^2),
-//                breakdown test, FP32 coefficients for the next kernels
-//   update       q_{j+1} = (w - alpha_j q_j) / beta_j
-// so each step streams the probe block a fixed number of times and the
-// reductions are deterministic (no floating-point atomics).
+// The vectors are kept unnormalized: R_j = beta_{j-1} q_j, R_1 = v (the +-1
+// probe), sigma_j = 1/||R_j||.  Per step j
+//   spmm_pieces   partial products sum_k A_ik D_c R_j[c] of the pieces of heavy rows
+//   spmm_rows     w = sigma_j L R_j - tau_{j-1} R_{j-1}  (tau_{j-1} = beta_{j-1} sigma_{j-1})
+//                 and FP64 partial sums of R_j . w
+//   finalize_a    alpha_j = sigma_j sum(R_j . w);  a_j = alpha_j sigma_j
+//   update        R_{j+1} = w - a_j R_j and FP64 partial sums of ||R_{j+1}||^2
+//   finalize_b    beta_j = ||R_{j+1}||, breakdown test, sigma_{j+1}, tau_j
+// which is the recurrence of §3.1 (w = L q_j - beta_{j-1} q_{j-1},
+// alpha_j = q_j.w, beta_j = ||w - alpha_j q_j||) with the scalings folded into
+// the reads.  Reductions are fixed-order (no floating-point atomics).
+//
+// Isolated nodes have zero rows and columns in L, so on them every R_j is a
+// multiple of the probe: R_j[i] = rho_j v[i] with rho_1 = 1, rho_0 = 0 and
+// rho_{j+1} = -tau_{j-1} rho_{j-1} - a_j rho_j.  Their rows are never stored
+// or streamed; their share of the two dot products is added in FP64 from
+// rho (v[i]^2 = 1) and the isolated-node count.
 #include <cmath>
 
 #include "common.hpp"
@@ -20,6 +27,17 @@
 namespace slaq {
 
 constexpr double kEpsBreakdown = 1e-6;
+
+// Per-probe FP64 recurrence state (workspace).
+struct ProbeState {
+    double sigma;     // 1 / ||R_j||
+    double tau;       // beta_{j-1} sigma_{j-1}
+    double rho;       // isolated-node coefficient of R_j
+    double rho_prev;  // ... of R_{j-1}
+    double a;         // alpha_j sigma_j
+    int active;
+    int pad;
+};
 
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) output number counter+1 for `seed`.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t counter) {
@@ -45,10 +63,38 @@ __device__ __forceinline__ void add4(float4& a, const float4& b) {
     a.w += b.w;
 }
 
+__device__ __forceinline__ float4 load4(const float* p, int q) {
+    return make_float4(p[4 * q], p[4 * q + 1], p[4 * q + 2], p[4 * q + 3]);
+}
+
+// Fixed-order reduction of per-lane FP64 sums (4 probes per lane) over the
+// groups of each wave and the 4 waves of the block; writes one partial per
+// probe of this block's tile: part[p * nb + block].
+__device__ __forceinline__ void block_reduce_store(const double (&s)[4], double* __restrict__ part, int nb,
+                                                   int F, int G, int K, int ld) {
+    __shared__ double red[4][64][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[wave][lane][c] = s[c];
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < 4 * G) {
+        const int q = t >> 2, comp = t & 3;
+        const int p = blockIdx.y * (4 * kQuadsPerTile) + t;
+        if (blockIdx.y * kQuadsPerTile + q < F && p < ld) {
+            double a = 0.0;
+            for (int wv = 0; wv < 4; ++wv)
+                for (int g = 0; g < K; ++g) a += red[wv][g * G + q][comp];
+            part[(int64_t)p * nb + blockIdx.x] = a;
+        }
+    }
+}
+
 // ------------------------------------------------------------- init -------
-__global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double* __restrict__ alpha,
-                                                  double* __restrict__ beta, int32_t* __restrict__ steps,
-                                                  int* __restrict__ active, float* __restrict__ coef) {
+__global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double sigma1,
+                                                  double* __restrict__ alpha, double* __restrict__ beta,
+                                                  int32_t* __restrict__ steps, ProbeState* __restrict__ ps,
+                                                  float* __restrict__ coef) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
     for (int k = t; k < nv * m; k += stride) {
@@ -56,18 +102,25 @@ __global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double*
         beta[k] = 0.0;
     }
     for (int p = t; p < ld; p += stride) {
-        if (p < nv) steps[p] = m;
-        active[p] = p < nv ? 1 : 0;
-        coef[p] = 0.0f;           // alpha
-        coef[ld + p] = 0.0f;      // 1 / beta
-        coef[2 * ld + p] = 0.0f;  // beta_{j-1}, zero before the first step
+        const bool on = p < nv;
+        if (on) steps[p] = m;
+        ps[p].sigma = on ? sigma1 : 0.0;
+        ps[p].tau = 0.0;
+        ps[p].rho = 1.0;
+        ps[p].rho_prev = 0.0;
+        ps[p].a = 0.0;
+        ps[p].active = on ? 1 : 0;
+        coef[p] = on ? (float)sigma1 : 0.0f;  // sigma_j
+        coef[ld + p] = 0.0f;                  // tau_{j-1}
+        coef[2 * ld + p] = 0.0f;              // a_j
     }
 }
 
-// q1[i][p] = +-1/sqrt(n): bit (p mod 64) of splitmix64(seed, 64 i + p div 64).
-// Thread layout: quad fixed per thread, rows strided (F divides the stride).
+// R_1[i][p] = +-1 (bit (p mod 64) of splitmix64(seed, 64 i + p div 64)) on
+// non-isolated rows; padding probes are 0.  One quad per thread, rows strided.
 __global__ void __launch_bounds__(256) probe_init(int64_t n, int nv, int F, int rows_per_sweep,
-                                                  uint64_t seed, float scale, float4* __restrict__ Q) {
+                                                  uint64_t seed, const float* __restrict__ diag,
+                                                  float4* __restrict__ R) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int quad = tid % F;
     const int64_t row0 = tid / F;
@@ -76,277 +129,387 @@ __global__ void __launch_bounds__(256) probe_init(int64_t n, int nv, int F, int 
     const uint64_t word = (uint64_t)(p0 >> 6);
     const int bit0 = p0 & 63;
     for (int64_t i = row0; i < n; i += rows_per_sweep) {
+        if (diag[i] == 0.0f) continue;
         const uint64_t z = splitmix64(seed, 64ull * (uint64_t)i + word);
         float v[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const float sgn = ((z >> (bit0 + c)) & 1ull) ? -scale : scale;
+            const float sgn = ((z >> (bit0 + c)) & 1ull) ? -1.0f : 1.0f;
             v[c] = (p0 + c < nv) ? sgn : 0.0f;
         }
-        Q[i * F + quad] = make_float4(v[0], v[1], v[2], v[3]);
+        R[i * F + quad] = make_float4(v[0], v[1], v[2], v[3]);
     }
 }
 
 // ------------------------------------------------------------- SpMM -------
-// Lane layout inside a wave: G lanes per group hold one float4 of probes each
-// (quad = tile*64 + lane%G), K = 64/G groups per wave work on different
-// nonzeros (chunks) or different rows (row kernel).
-
-// acc += sum_{k in [k0,k1), step} scale_k * Q[col_k], four loads in flight.
+// Gather-accumulate over nonzeros [k0, k1) of one row by the group of this
+// lane: the group loads up to G column indices (and their scale) at once and
+// broadcasts them with lane shuffles; gathers are issued four at a time.
 template <int MODE, bool WEIGHTED>
-__device__ __forceinline__ void row_segment(float4& acc, int64_t k0, int64_t k1, int step,
-                                            const int32_t* __restrict__ col,
-                                            const float* __restrict__ w,
-                                            const float* __restrict__ diag,
-                                            const float4* __restrict__ Q, int F, int quad) {
-    int64_t k = k0;
-    for (; k + 3 * (int64_t)step < k1; k += 4 * (int64_t)step) {
-        int32_t c[4];
-        float s[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = col[k + u * step];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            float sc = WEIGHTED ? w[k + u * step] : 1.0f;
-            if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[c[u]];
-            s[u] = sc;
+__device__ __forceinline__ void group_segment(float4& acc, int64_t k0, int64_t k1, int gbase, int gl, int G,
+                                              const int32_t* __restrict__ col, const float* __restrict__ w,
+                                              const float* __restrict__ diag, const float4* __restrict__ R,
+                                              int F, int quad, bool lane_ok) {
+    for (int64_t kb = k0; kb < k1; kb += G) {
+        const int cnt = (int)((k1 - kb) < G ? (k1 - kb) : G);
+        int32_t cl = 0;
+        float sl = 0.0f;
+        if (gl < cnt) {
+            cl = col[kb + gl];
+            float sc = WEIGHTED ? w[kb + gl] : 1.0f;
+            if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[cl];
+            sl = sc;
         }
-        float4 x[4];
+        int u = 0;
+        for (; u + 4 <= cnt; u += 4) {
+            int32_t c[4];
+            float s[4];
+            float4 x[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = Q[(int64_t)c[u] * F + quad];
+            for (int v = 0; v < 4; ++v) {
+                c[v] = __shfl(cl, gbase + u + v);
+                s[v] = __shfl(sl, gbase + u + v);
+            }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) fma4(s[u], x[u], acc);
-    }
-    for (; k < k1; k += step) {
-        const int32_t c = col[k];
-        float sc = WEIGHTED ? w[k] : 1.0f;
-        if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[c];
-        fma4(sc, Q[(int64_t)c * F + quad], acc);
+            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? R[(int64_t)c[v] * F + quad] : f4(0.0f);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) fma4(s[v], x[v], acc);
+        }
+        for (; u < cnt; ++u) {
+            const int32_t c = __shfl(cl, gbase + u);
+            const float s = __shfl(sl, gbase + u);
+            if (lane_ok) fma4(s, R[(int64_t)c * F + quad], acc);
+        }
     }
 }
 
-// smallest r with rp[r+1] > k (the row holding nonzero k)
-__device__ __forceinline__ int64_t row_of(const int64_t* __restrict__ rp, int64_t n, int64_t k) {
-    int64_t lo = 0, hi = n;
+// largest h with hoff[h] <= p (hoff increasing, hoff[nh] > p)
+__device__ __forceinline__ int64_t piece_owner(const int64_t* __restrict__ hoff, int64_t nh, int64_t p) {
+    int64_t lo = 0, hi = nh - 1;
     while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (rp[mid + 1] <= k) lo = mid + 1; else hi = mid;
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (hoff[mid] <= p) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-// Heavy rows (degree >= kHeavyMin): chunk c = nonzeros [c*kChunk, (c+1)*kChunk)
-// lying wholly inside one heavy row gets H[c] = sum scale_k Q[col_k].
+// index of row i in the increasing list hrow[0..nh)
+__device__ __forceinline__ int64_t heavy_index(const int32_t* __restrict__ hrow, int64_t nh, int64_t i) {
+    int64_t lo = 0, hi = nh;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)hrow[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// One wave per piece: P[p] = sum over the piece's nonzeros of scale * R_j[col].
 template <int MODE, bool WEIGHTED>
-__global__ void __launch_bounds__(256) spmm_chunks(int64_t n, int64_t nchunks,
+__global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict__ st,
+                                                   const int32_t* __restrict__ hrow,
+                                                   const int64_t* __restrict__ hoff,
                                                    const int64_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col,
                                                    const float* __restrict__ w,
                                                    const float* __restrict__ diag,
-                                                   const float4* __restrict__ Q,
-                                                   float4* __restrict__ H, int F, int G, int K) {
+                                                   const float4* __restrict__ R,
+                                                   float4* __restrict__ P, int F, int G, int K, int piece) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int quad = blockIdx.y * kQuadsPerTile + gl;
-    const bool lane_ok = gi < K && quad < F;
-    for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < nchunks; c += (int64_t)gridDim.x * 4) {
-        const int64_t k0 = c * kChunk, k1 = k0 + kChunk;
-        const int64_t r = row_of(rp, n, k0);
-        const int64_t s = rp[r], e = rp[r + 1];
-        if (e - s < kHeavyMin || s > k0 || e < k1) continue;  // wave-uniform
+    const bool in_group = gi < K;
+    const bool lane_ok = in_group && quad < F;
+    const int64_t np = st->n_pieces, nh = st->n_heavy;
+    for (int64_t p = (int64_t)blockIdx.x * 4 + wave; p < np; p += (int64_t)gridDim.x * 4) {
+        const int64_t h = piece_owner(hoff, nh, p);
+        const int64_t row = hrow[h];
+        const int64_t e = rp[row + 1];
+        const int64_t k0 = rp[row] + (p - hoff[h]) * piece;
+        const int64_t k1 = k0 + piece < e ? k0 + piece : e;
         float4 acc = f4(0.0f);
-        if (lane_ok)
-            row_segment<MODE, WEIGHTED>(acc, k0 + gi, k1, K, col, w, diag, Q, F, quad);
-        // fixed-order tree over the K groups (lane + s*G)
-        for (int st = 1; st < K; st <<= 1) {
-            const int src = lane + st * G < 64 ? lane + st * G : lane;
+        // the wave loads 64 column indices at a time; group gi takes u = gi, gi+K, ...
+        for (int64_t kb = k0; kb < k1; kb += 64) {
+            const int cnt = (int)((k1 - kb) < 64 ? (k1 - kb) : 64);
+            int32_t cl = 0;
+            float sl = 0.0f;
+            if (lane < cnt) {
+                cl = col[kb + lane];
+                float sc = WEIGHTED ? w[kb + lane] : 1.0f;
+                if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[cl];
+                sl = sc;
+            }
+            const int rounds = (cnt + K - 1) / K;
+            int r = 0;
+            for (; r + 4 <= rounds; r += 4) {
+                int32_t c[4];
+                float s[4];
+                float4 x[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int u = (r + v) * K + gi;
+                    const int src = u < 64 ? u : 63;
+                    c[v] = __shfl(cl, src);
+                    s[v] = __shfl(sl, src);
+                    if (!(in_group && u < cnt)) s[v] = 0.0f;
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) x[v] = (lane_ok && s[v] != 0.0f) ? R[(int64_t)c[v] * F + quad] : f4(0.0f);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) fma4(s[v], x[v], acc);
+            }
+            for (; r < rounds; ++r) {
+                const int u = r * K + gi;
+                const int src = u < 64 ? u : 63;
+                const int32_t c = __shfl(cl, src);
+                const float s = __shfl(sl, src);
+                if (lane_ok && u < cnt) fma4(s, R[(int64_t)c * F + quad], acc);
+            }
+        }
+        // fixed-order tree over the K groups (lane + st*G)
+        for (int sd = 1; sd < K; sd <<= 1) {
+            const int src = lane + sd * G < 64 ? lane + sd * G : lane;
             float4 o;
             o.x = __shfl(acc.x, src);
             o.y = __shfl(acc.y, src);
             o.z = __shfl(acc.z, src);
             o.w = __shfl(acc.w, src);
-            if ((gi % (2 * st)) == 0 && gi + st < K) add4(acc, o);
+            if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) add4(acc, o);
         }
-        if (gi == 0 && quad < F) H[c * F + quad] = acc;
+        if (gi == 0 && quad < F) P[p * F + quad] = acc;
     }
 }
 
-// Every row: w_i = L q_j (row i) - beta_{j-1} q_{j-1}[i]; FP64 partial dots.
+// Every non-isolated row: w = sigma (L R_j)_i - tau R_{j-1}[i]; partial R_j.w.
+// A wave takes windows of 64 rows (row offsets loaded by its lanes at once);
+// group gi handles rows gi, gi+K, ... of the window.
 template <int MODE, bool WEIGHTED>
 __global__ void __launch_bounds__(256) spmm_rows(int64_t n, const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ w,
                                                  const float* __restrict__ diag,
-                                                 const float4* __restrict__ Q,
-                                                 const float4* __restrict__ Qp,
-                                                 const float4* __restrict__ H,
-                                                 float4* __restrict__ W,
-                                                 const float* __restrict__ cB, int has_prev,
-                                                 double* __restrict__ part, int nb, int F, int G,
-                                                 int K, int ld) {
+                                                 const GraphStats* __restrict__ st,
+                                                 const int32_t* __restrict__ hrow,
+                                                 const int64_t* __restrict__ hoff,
+                                                 const float4* __restrict__ P, int heavy_min,
+                                                 const float4* __restrict__ R,
+                                                 const float4* __restrict__ Rp,
+                                                 float4* __restrict__ W, const float* __restrict__ coef,
+                                                 int has_prev, double* __restrict__ part, int nb, int F, int G,
+                                                 int K, int ld, int rw) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gi = lane / G, gl = lane % G;
+    const int gbase = gi * G;
+    const int quad = blockIdx.y * kQuadsPerTile + gl;
+    const bool in_group = gi < K;
+    const bool lane_ok = in_group && quad < F;
+    const int64_t nh = st->n_heavy;
+
+    double s1[4] = {0.0, 0.0, 0.0, 0.0};
+    float4 sg = f4(0.0f), tp = f4(0.0f);
+    if (lane_ok) {
+        sg = load4(coef, quad);
+        if (has_prev) tp = load4(coef + ld, quad);
+    }
+    const int rounds = (rw + K - 1) / K;
+    const int64_t nwin = (n + rw - 1) / rw;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += nwaves) {
+        const int64_t r0 = win * rw;
+        const int64_t ia = r0 + lane < n ? r0 + lane : n;
+        const int64_t ib = r0 + lane + 1 < n ? r0 + lane + 1 : n;
+        const int64_t rs_l = rp[ia], re_l = rp[ib];
+        for (int rr = 0; rr < rounds; ++rr) {
+            const int t = rr * K + gi;
+            const int src = t < 64 ? t : 63;
+            const int64_t s = __shfl(rs_l, src), e = __shfl(re_l, src);
+            const int64_t i = r0 + t;
+            if (!in_group || t >= rw || i >= n || e == s) continue;  // isolated: nothing stored
+            float4 acc = f4(0.0f);
+            int64_t h = nh;
+            if (e - s >= heavy_min) {
+                h = heavy_index(hrow, nh, i);
+                if (h < nh && (int64_t)hrow[h] != i) h = nh;  // not in the plan: compute directly
+            }
+            if (h < nh) {
+                const int64_t p0 = hoff[h], p1 = hoff[h + 1];
+                int64_t p = p0;
+                for (; p + 4 <= p1; p += 4) {
+                    float4 x[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x[v] = lane_ok ? P[(p + v) * F + quad] : f4(0.0f);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) add4(acc, x[v]);
+                }
+                for (; p < p1; ++p)
+                    if (lane_ok) add4(acc, P[p * F + quad]);
+            } else {
+                group_segment<MODE, WEIGHTED>(acc, s, e, gbase, gl, G, col, w, diag, R, F, quad, lane_ok);
+            }
+            if (!lane_ok) continue;
+            const float4 ri = R[i * F + quad];
+            const float di = diag[i];
+            float4 lr;  // (L R_j)_i
+            if (MODE == SLAQ_LAP_NORMALIZED) {
+                lr.x = fmaf(-di, acc.x, ri.x);
+                lr.y = fmaf(-di, acc.y, ri.y);
+                lr.z = fmaf(-di, acc.z, ri.z);
+                lr.w = fmaf(-di, acc.w, ri.w);
+            } else {
+                lr.x = fmaf(di, ri.x, -acc.x);
+                lr.y = fmaf(di, ri.y, -acc.y);
+                lr.z = fmaf(di, ri.z, -acc.z);
+                lr.w = fmaf(di, ri.w, -acc.w);
+            }
+            float4 wi = make_float4(sg.x * lr.x, sg.y * lr.y, sg.z * lr.z, sg.w * lr.w);
+            if (has_prev) {
+                const float4 rq = Rp[i * F + quad];
+                wi.x = fmaf(-tp.x, rq.x, wi.x);
+                wi.y = fmaf(-tp.y, rq.y, wi.y);
+                wi.z = fmaf(-tp.z, rq.z, wi.z);
+                wi.w = fmaf(-tp.w, rq.w, wi.w);
+            }
+            W[i * F + quad] = wi;
+            // products of two floats are exact in double
+            s1[0] = fma((double)ri.x, (double)wi.x, s1[0]);
+            s1[1] = fma((double)ri.y, (double)wi.y, s1[1]);
+            s1[2] = fma((double)ri.z, (double)wi.z, s1[2]);
+            s1[3] = fma((double)ri.w, (double)wi.w, s1[3]);
+        }
+    }
+    block_reduce_store(s1, part, nb, F, G, K, ld);
+}
+
+// R_{j+1} = w - a_j R_j on non-isolated rows (stored when `store`), partial
+// sums of ||R_{j+1}||^2.  Same wave/group layout as spmm_rows.
+__global__ void __launch_bounds__(256) update(int64_t n, const float* __restrict__ diag,
+                                              const float4* __restrict__ W, const float4* __restrict__ R,
+                                              const float* __restrict__ coef, int store,
+                                              float4* __restrict__ Rn, double* __restrict__ part, int nb,
+                                              int F, int G, int K, int ld, int rw) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int quad = blockIdx.y * kQuadsPerTile + gl;
-    const bool lane_ok = gi < K && quad < F;
-
-    double s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0}, s3[4] = {0, 0, 0, 0};
-    float4 bprev = f4(0.0f);
-    if (has_prev && lane_ok) bprev = make_float4(cB[4 * quad], cB[4 * quad + 1], cB[4 * quad + 2], cB[4 * quad + 3]);
-
-    const int64_t nwin = (n + K - 1) / K;
-    if (lane_ok) {
-        for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += (int64_t)nb * 4) {
-            const int64_t i = win * K + gi;
-            if (i >= n) break;
-            const int64_t s = rp[i], e = rp[i + 1];
-            float4 acc = f4(0.0f);
-            if (e - s >= kHeavyMin) {
-                const int64_t c0 = (s + kChunk - 1) / kChunk, c1 = e / kChunk;
-                for (int64_t c = c0; c < c1; ++c) add4(acc, H[c * F + quad]);
-                row_segment<MODE, WEIGHTED>(acc, s, c0 * kChunk, 1, col, w, diag, Q, F, quad);
-                row_segment<MODE, WEIGHTED>(acc, c1 * kChunk, e, 1, col, w, diag, Q, F, quad);
-            } else {
-                row_segment<MODE, WEIGHTED>(acc, s, e, 1, col, w, diag, Q, F, quad);
-            }
-            const float4 qi = Q[i * F + quad];
-            const float di = diag[i];
-            float4 wi;
-            if (MODE == SLAQ_LAP_NORMALIZED) {
-                const float id = di > 0.0f ? 1.0f : 0.0f;
-                wi.x = fmaf(-di, acc.x, id * qi.x);
-                wi.y = fmaf(-di, acc.y, id * qi.y);
-                wi.z = fmaf(-di, acc.z, id * qi.z);
-                wi.w = fmaf(-di, acc.w, id * qi.w);
-            } else {
-                wi.x = fmaf(di, qi.x, -acc.x);
-                wi.y = fmaf(di, qi.y, -acc.y);
-                wi.z = fmaf(di, qi.z, -acc.z);
-                wi.w = fmaf(di, qi.w, -acc.w);
-            }
-            if (has_prev) {
-                const float4 qp = Qp[i * F + quad];
-                wi.x = fmaf(-bprev.x, qp.x, wi.x);
-                wi.y = fmaf(-bprev.y, qp.y, wi.y);
-                wi.z = fmaf(-bprev.z, qp.z, wi.z);
-                wi.w = fmaf(-bprev.w, qp.w, wi.w);
-            }
-            W[i * F + quad] = wi;
-            const float qv[4] = {qi.x, qi.y, qi.z, qi.w};
-            const float wv[4] = {wi.x, wi.y, wi.z, wi.w};
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                // products of two floats are exact in double
-                s1[c] = fma((double)qv[c], (double)wv[c], s1[c]);
-                s2[c] = fma((double)wv[c], (double)wv[c], s2[c]);
-                s3[c] = fma((double)qv[c], (double)qv[c], s3[c]);
-            }
+    const bool in_group = gi < K;
+    const bool lane_ok = in_group && quad < F;
+    double s2[4] = {0.0, 0.0, 0.0, 0.0};
+    float4 a = f4(0.0f);
+    if (lane_ok) a = load4(coef + 2 * ld, quad);
+    const int rounds = (rw + K - 1) / K;
+    const int64_t nwin = (n + rw - 1) / rw;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += nwaves) {
+        const int64_t r0 = win * rw;
+        const float d_l = r0 + lane < n ? diag[r0 + lane] : 0.0f;
+        for (int rr = 0; rr < rounds; ++rr) {
+            const int t = rr * K + gi;
+            const float d = __shfl(d_l, t < 64 ? t : 63);
+            const int64_t i = r0 + t;
+            if (!lane_ok || t >= rw || i >= n || d == 0.0f) continue;
+            const float4 wv = W[i * F + quad];
+            const float4 rv = R[i * F + quad];
+            float4 r;
+            r.x = fmaf(-a.x, rv.x, wv.x);
+            r.y = fmaf(-a.y, rv.y, wv.y);
+            r.z = fmaf(-a.z, rv.z, wv.z);
+            r.w = fmaf(-a.w, rv.w, wv.w);
+            if (store) Rn[i * F + quad] = r;
+            s2[0] = fma((double)r.x, (double)r.x, s2[0]);
+            s2[1] = fma((double)r.y, (double)r.y, s2[1]);
+            s2[2] = fma((double)r.z, (double)r.z, s2[2]);
+            s2[3] = fma((double)r.w, (double)r.w, s2[3]);
         }
     }
-
-    // block reduction in fixed order: waves, then groups
-    __shared__ double red[4][64][12];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        red[wave][lane][c] = s1[c];
-        red[wave][lane][4 + c] = s2[c];
-        red[wave][lane][8 + c] = s3[c];
-    }
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t < 4 * G) {
-        const int q = t >> 2, comp = t & 3;
-        const int p = blockIdx.y * (4 * kQuadsPerTile) + t;
-        if (blockIdx.y * kQuadsPerTile + q < F && p < ld) {
-            double a[3] = {0.0, 0.0, 0.0};
-            for (int wv = 0; wv < 4; ++wv)
-                for (int g = 0; g < K; ++g)
-#pragma unroll
-                    for (int sidx = 0; sidx < 3; ++sidx) a[sidx] += red[wv][g * G + q][4 * sidx + comp];
-#pragma unroll
-            for (int sidx = 0; sidx < 3; ++sidx) part[((int64_t)sidx * ld + p) * nb + blockIdx.x] = a[sidx];
-        }
-    }
+    block_reduce_store(s2, part, nb, F, G, K, ld);
 }
 
 // ---------------------------------------------------------- finalize ------
-__global__ void __launch_bounds__(256) finalize(const double* __restrict__ part, int nb, int ld, int m,
-                                                int j, const GraphStats* __restrict__ st, int laplacian,
-                                                double eps_bd, double* __restrict__ alpha,
-                                                double* __restrict__ beta, int32_t* __restrict__ steps,
-                                                int* __restrict__ active, float* __restrict__ coef) {
-    const int p = blockIdx.x, t = threadIdx.x;
-    double a[3] = {0.0, 0.0, 0.0};
-    for (int b = t; b < nb; b += 256)
-#pragma unroll
-        for (int s = 0; s < 3; ++s) a[s] += part[((int64_t)s * ld + p) * nb + b];
-    __shared__ double red[3][256];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) red[s][t] = a[s];
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nb, int p) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (int b = t; b < nb; b += 256) a += part[(int64_t)p * nb + b];
+    red[t] = a;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-        if (t < off)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) red[s][t] += red[s][t + off];
+        if (t < off) red[t] += red[t + off];
         __syncthreads();
     }
-    if (t != 0) return;
-    if (!active[p]) {
-        coef[p] = 0.0f;
-        coef[ld + p] = 0.0f;
+    return red[0];
+}
+
+__global__ void __launch_bounds__(256) finalize_a(const double* __restrict__ part, int nb, int ld, int m, int j,
+                                                  const GraphStats* __restrict__ st, ProbeState* __restrict__ ps,
+                                                  double* __restrict__ alpha, float* __restrict__ coef) {
+    const int p = blockIdx.x;
+    const double s1 = sum_partials(part, nb, p);
+    if (threadIdx.x != 0) return;
+    ProbeState s = ps[p];
+    if (!s.active) {
         coef[2 * ld + p] = 0.0f;
         return;
     }
-    const double qw = red[0][0], ww = red[1][0], qq = red[2][0];
-    const double al = qw;
-    const double b2 = ww - 2.0 * al * qw + al * al * qq;
-    const double be = sqrt(fmax(b2, 0.0));
+    // isolated rows: R_j[i] = rho_j v_i, w_i = -tau_{j-1} rho_{j-1} v_i
+    const double iso = (double)st->n_isolated * s.rho * (-s.tau * s.rho_prev);
+    const double al = s.sigma * (s1 + iso);
     alpha[(int64_t)p * m + (j - 1)] = al;
+    s.a = al * s.sigma;
+    ps[p].a = s.a;
+    coef[2 * ld + p] = (float)s.a;
+}
+
+__global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ part, int nb, int ld, int m, int j,
+                                                  const GraphStats* __restrict__ st, int laplacian, double eps_bd,
+                                                  ProbeState* __restrict__ ps, double* __restrict__ beta,
+                                                  int32_t* __restrict__ steps, float* __restrict__ coef) {
+    const int p = blockIdx.x;
+    const double s2 = sum_partials(part, nb, p);
+    if (threadIdx.x != 0) return;
+    ProbeState s = ps[p];
+    if (!s.active) return;
+    const double rho_next = -s.tau * s.rho_prev - s.a * s.rho;
+    const double nrm2 = s2 + (double)st->n_isolated * rho_next * rho_next;
+    const double be = sqrt(fmax(nrm2, 0.0));
     beta[(int64_t)p * m + (j - 1)] = be;
     const double bound = laplacian == SLAQ_LAP_NORMALIZED ? 2.0 : 2.0 * st->max_degree;
     if (j < m && !(be > eps_bd * bound)) {
         steps[p] = j;
-        active[p] = 0;
+        s.active = 0;
+        s.sigma = 0.0;
+        s.tau = 0.0;
         coef[p] = 0.0f;
         coef[ld + p] = 0.0f;
         coef[2 * ld + p] = 0.0f;
     } else {
-        coef[p] = (float)al;
-        coef[ld + p] = (float)(1.0 / be);
-        coef[2 * ld + p] = (float)be;
+        s.tau = be * s.sigma;
+        s.sigma = 1.0 / be;
+        s.rho_prev = s.rho;
+        s.rho = rho_next;
+        coef[p] = (float)s.sigma;
+        coef[ld + p] = (float)s.tau;
     }
-}
-
-// q_{j+1} = (w - alpha q_j) / beta, per probe; zero for stopped probes.
-__global__ void __launch_bounds__(256) update(int64_t n, int F, int rows_per_sweep,
-                                              const float4* __restrict__ W,
-                                              const float4* __restrict__ Q,
-                                              const float* __restrict__ coef, int ld,
-                                              float4* __restrict__ Qn) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int quad = tid % F;
-    const int64_t row0 = tid / F;
-    if (row0 >= rows_per_sweep) return;
-    const float4 a = make_float4(coef[4 * quad], coef[4 * quad + 1], coef[4 * quad + 2], coef[4 * quad + 3]);
-    const float4 ib = make_float4(coef[ld + 4 * quad], coef[ld + 4 * quad + 1], coef[ld + 4 * quad + 2],
-                                  coef[ld + 4 * quad + 3]);
-    for (int64_t i = row0; i < n; i += rows_per_sweep) {
-        const float4 wv = W[i * F + quad];
-        const float4 qv = Q[i * F + quad];
-        float4 r;
-        r.x = fmaf(-a.x, qv.x, wv.x) * ib.x;
-        r.y = fmaf(-a.y, qv.y, wv.y) * ib.y;
-        r.z = fmaf(-a.z, qv.z, wv.z) * ib.z;
-        r.w = fmaf(-a.w, qv.w, wv.w) * ib.w;
-        Qn[i * F + quad] = r;
-    }
+    ps[p] = s;
 }
 
 // ------------------------------------------------------------ layout ------
 struct Layout {
-    int ld, F, G, K, ntiles, nb;
-    int64_t nchunks;
-    size_t vec_bytes, off_q[3], off_h, off_part, off_coef, off_active, total;
+    int ld, F, G, K, ntiles, nb_rows, nb_upd, piece_blocks, rw;
+    int64_t max_pieces;
+    size_t off_r[3], off_p, off_part1, off_part2, off_ps, off_coef, total;
 };
+
+constexpr int kRowBlocks = 2048;  // upper bound; the grid is sized to what stays resident
+constexpr int kPieceBlocks = 4096;
+
+// Blocks of `kernel` that fit on the current device at once (all CUs).
+template <typename K>
+static int resident_blocks(K kernel, int block) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kRowBlocks;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return kRowBlocks;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+        return kRowBlocks;
+    return cus * per_cu;
+}
 
 static Layout make_layout(const slaq_graph_s* g, int nv) {
     Layout L{};
@@ -355,30 +518,49 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     L.G = L.F < kQuadsPerTile ? L.F : kQuadsPerTile;
     L.K = 64 / L.G;
     L.ntiles = (L.F + kQuadsPerTile - 1) / kQuadsPerTile;
-    const int64_t nwin = (g->n + L.K - 1) / L.K;
+    // rows per wave window: up to 64, fewer on small graphs so that the
+    // windows still cover every resident wave (never fewer than K)
+    const int64_t target_waves = 8192;
+    int64_t rw = (g->n + target_waves - 1) / target_waves;
+    if (rw > kRowsPerWindow) rw = kRowsPerWindow;
+    if (rw < L.K) rw = L.K;
+    L.rw = (int)rw;
+    const int64_t nwin = (g->n + L.rw - 1) / L.rw;
     int64_t nb = (nwin + 3) / 4;
-    L.nb = (int)(nb < kSpmmMaxBlocks ? (nb > 0 ? nb : 1) : kSpmmMaxBlocks);
-    L.nchunks = g->nnz / kChunk;
-    L.vec_bytes = align_up((size_t)g->n * L.ld * sizeof(float), 256);
+    if (nb < 1) nb = 1;
+    static const int rows_cap = resident_blocks(spmm_rows<SLAQ_LAP_NORMALIZED, false>, kSpmmBlock);
+    static const int upd_cap = resident_blocks(update, kSpmmBlock);
+    const int cap_r = rows_cap < kRowBlocks ? rows_cap : kRowBlocks;
+    const int cap_u = upd_cap < kRowBlocks ? upd_cap : kRowBlocks;
+    L.nb_rows = (int)(nb < cap_r ? nb : cap_r);
+    L.nb_upd = (int)(nb < cap_u ? nb : cap_u);
+    // pieces <= nnz/piece + one partial piece per heavy row
+    int64_t heavy_cap = g->nnz / g->heavy_min;
+    if (heavy_cap > g->n) heavy_cap = g->n;
+    L.max_pieces = g->nnz / g->piece + heavy_cap;
+    int64_t pb = (L.max_pieces + 3) / 4;
+    L.piece_blocks = (int)(pb < kPieceBlocks ? (pb > 0 ? pb : 1) : kPieceBlocks);
+    const size_t vec = align_up((size_t)g->n * L.ld * sizeof(float), 256);
     size_t off = 0;
     for (int b = 0; b < 3; ++b) {
-        L.off_q[b] = off;
-        off += L.vec_bytes;
+        L.off_r[b] = off;
+        off += vec;
     }
-    L.off_h = off;
-    off += align_up((size_t)L.nchunks * L.ld * sizeof(float), 256);
-    L.off_part = off;
-    off += align_up((size_t)3 * L.ld * L.nb * sizeof(double), 256);
+    L.off_p = off;
+    off += align_up((size_t)L.max_pieces * L.ld * sizeof(float), 256);
+    L.off_part1 = off;
+    off += align_up((size_t)L.ld * L.nb_rows * sizeof(double), 256);
+    L.off_part2 = off;
+    off += align_up((size_t)L.ld * L.nb_upd * sizeof(double), 256);
+    L.off_ps = off;
+    off += align_up((size_t)L.ld * sizeof(ProbeState), 256);
     L.off_coef = off;
     off += align_up((size_t)3 * L.ld * sizeof(float), 256);
-    L.off_active = off;
-    off += align_up((size_t)L.ld * sizeof(int), 256);
     L.total = off;
     return L;
 }
 
 static int sweep_grid(int64_t n, int F, int* rows_per_sweep) {
-    // threads = F * rows, capped; every thread keeps one quad
     int64_t rows = n;
     const int64_t max_threads = 256LL * 8192;
     if ((int64_t)F * rows > max_threads) rows = max_threads / F;
@@ -391,15 +573,15 @@ static int sweep_grid(int64_t n, int F, int* rows_per_sweep) {
 
 using namespace slaq;
 
-#define SLAQ_DISPATCH(MODE_, WEIGHTED_, KERNEL, ...)                                         \
-    do {                                                                                      \
-        if ((MODE_) == SLAQ_LAP_NORMALIZED) {                                                 \
-            if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, true>), __VA_ARGS__);   \
-            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, false>), __VA_ARGS__);            \
-        } else {                                                                              \
+#define SLAQ_DISPATCH(MODE_, WEIGHTED_, KERNEL, ...)                                               \
+    do {                                                                                            \
+        if ((MODE_) == SLAQ_LAP_NORMALIZED) {                                                       \
+            if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, true>), __VA_ARGS__);    \
+            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, false>), __VA_ARGS__);             \
+        } else {                                                                                    \
             if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, true>), __VA_ARGS__); \
-            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, false>), __VA_ARGS__);         \
-        }                                                                                     \
+            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, false>), __VA_ARGS__);          \
+        }                                                                                           \
     } while (0)
 
 extern "C" {
@@ -429,48 +611,53 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
                  L.total, workspace_bytes);
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
-    float4* Qb[3] = {(float4*)(ws + L.off_q[0]), (float4*)(ws + L.off_q[1]), (float4*)(ws + L.off_q[2])};
-    float4* H = (float4*)(ws + L.off_h);
-    double* part = (double*)(ws + L.off_part);
+    float4* Rb[3] = {(float4*)(ws + L.off_r[0]), (float4*)(ws + L.off_r[1]), (float4*)(ws + L.off_r[2])};
+    float4* P = (float4*)(ws + L.off_p);
+    double* part1 = (double*)(ws + L.off_part1);
+    double* part2 = (double*)(ws + L.off_part2);
+    ProbeState* ps = (ProbeState*)(ws + L.off_ps);
     float* coef = (float*)(ws + L.off_coef);
-    int* active = (int*)(ws + L.off_active);
     const int mode = g->laplacian;
     const bool weighted = g->weights != nullptr;
 
-    hipLaunchKernelGGL(state_init, dim3(4), dim3(256), 0, st, nv, m, L.ld, alpha, beta, steps, active, coef);
+    const double sigma1 = 1.0 / sqrt((double)g->n);
+    hipLaunchKernelGGL(state_init, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef);
     SLAQ_LAUNCHED();
     int rps = 0;
     const int sgrid = sweep_grid(g->n, L.F, &rps);
-    const float scale = (float)(1.0 / sqrt((double)g->n));
-    hipLaunchKernelGGL(probe_init, dim3(sgrid), dim3(256), 0, st, g->n, nv, L.F, rps, seed, scale, Qb[0]);
+    hipLaunchKernelGGL(probe_init, dim3(sgrid), dim3(256), 0, st, g->n, nv, L.F, rps, seed, g->diag, Rb[0]);
     SLAQ_LAUNCHED();
 
     int cur = 0, prev = 1;
     const int wbuf = 2;
-    const int64_t chunk_blocks64 = (L.nchunks + 3) / 4;
-    const int chunk_blocks = (int)(chunk_blocks64 < 4096 ? chunk_blocks64 : 4096);
     for (int j = 1; j <= m; ++j) {
-        if (L.nchunks > 0) {
-            SLAQ_TIMED("spmm_chunks", st,
-                       SLAQ_DISPATCH(mode, weighted, spmm_chunks, dim3(chunk_blocks, L.ntiles), dim3(256), 0, st,
-                                     g->n, L.nchunks, g->row_ptr, g->col_idx, g->weights, g->diag, Qb[cur], H,
-                                     L.F, L.G, L.K));
+        if (L.max_pieces > 0) {
+            SLAQ_TIMED("spmm_pieces", st,
+                       SLAQ_DISPATCH(mode, weighted, spmm_pieces, dim3(L.piece_blocks, L.ntiles), dim3(256), 0, st,
+                                     g->stats, g->hrow, g->hoff, g->row_ptr, g->col_idx, g->weights, g->diag,
+                                     Rb[cur], P, L.F, L.G, L.K, g->piece));
             SLAQ_LAUNCHED();
         }
         SLAQ_TIMED("spmm_rows", st,
-                   SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb, L.ntiles), dim3(kSpmmBlock), 0, st, g->n,
-                                 g->row_ptr, g->col_idx, g->weights, g->diag, Qb[cur], Qb[prev], H, Qb[wbuf],
-                                 coef + 2 * L.ld, j > 1 ? 1 : 0, part, L.nb, L.F, L.G, L.K, L.ld));
+                   SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, L.ntiles), dim3(kSpmmBlock), 0, st,
+                                 g->n, g->row_ptr, g->col_idx, g->weights, g->diag, g->stats, g->hrow, g->hoff, P,
+                                 g->heavy_min, Rb[cur], Rb[prev], Rb[wbuf], coef, j > 1 ? 1 : 0, part1, L.nb_rows,
+                                 L.F, L.G, L.K, L.ld, L.rw));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
-                   hipLaunchKernelGGL(finalize, dim3(nv), dim3(256), 0, st, part, L.nb, L.ld, m, j, g->stats, mode,
-                                      kEpsBreakdown, alpha, beta, steps, active, coef));
+                   hipLaunchKernelGGL(finalize_a, dim3(nv), dim3(256), 0, st, part1, L.nb_rows, L.ld, m, j,
+                                      g->stats, ps, alpha, coef));
+        SLAQ_LAUNCHED();
+        SLAQ_TIMED("update", st,
+                   hipLaunchKernelGGL(update, dim3(L.nb_upd, L.ntiles), dim3(kSpmmBlock), 0, st, g->n, g->diag,
+                                      Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F, L.G,
+                                      L.K, L.ld, L.rw));
+        SLAQ_LAUNCHED();
+        SLAQ_TIMED("finalize", st,
+                   hipLaunchKernelGGL(finalize_b, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,
+                                      g->stats, mode, kEpsBreakdown, ps, beta, steps, coef));
         SLAQ_LAUNCHED();
         if (j < m) {
-            SLAQ_TIMED("update", st,
-                       hipLaunchKernelGGL(update, dim3(sgrid), dim3(256), 0, st, g->n, L.F, rps, Qb[wbuf], Qb[cur],
-                                          coef, L.ld, Qb[prev]));
-            SLAQ_LAUNCHED();
             const int t = cur;
             cur = prev;
             prev = t;

@@ -36,6 +36,9 @@ SIGNATURES = {
     "slaq_graph_info": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                         ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
     "slaq_graph_destroy": [_vp],
+    "slaq_graph_set_schedule": [_vp, _int, _int, _vp],
+    "slaq_graph_schedule": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
+                            ctypes.POINTER(_i64)],
     "slaq_lanczos_workspace": [_vp, _int, _int, ctypes.POINTER(_sz)],
     "slaq_lanczos": [_vp, _int, _int, ctypes.c_uint64, _vp, _vp, _vp, _vp, _sz, _vp],
     "slaq_ritz": [_vp, _vp, _vp, _int, _int, _vp, _vp, _vp],
@@ -122,6 +125,15 @@ class Graph:
                                      ctypes.byref(iso), ctypes.byref(mx)))
         return {"n": n.value, "nnz": nnz.value, "trace": tr.value, "n_isolated": iso.value,
                 "max_degree": mx.value}
+
+    def set_schedule(self, heavy_min, piece, stream=None):
+        _check(lib().slaq_graph_set_schedule(self.handle, heavy_min, piece, _stream(stream)))
+
+    def schedule(self):
+        hm, pc, nh, npc = _int(), _int(), _i64(), _i64()
+        _check(lib().slaq_graph_schedule(self.handle, ctypes.byref(hm), ctypes.byref(pc), ctypes.byref(nh),
+                                         ctypes.byref(npc)))
+        return {"heavy_min": hm.value, "piece": pc.value, "n_heavy": nh.value, "n_pieces": npc.value}
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -89,18 +89,45 @@ def test_degenerate_graphs(case):
     gpu = gpu_run(csr, nv, m, 5, T256)
     ora = oracle_run(csr, nv, m, 5, T256)
     # After an exact breakdown the FP32 residual is rounding noise amplified by
-    # 1/beta of earlier steps (about sqrt(n/2) on a star), so the GPU may carry
-    # on past the FP64 stopping step into directions whose Gauss weights are
-    # O(noise^2).  Coefficients are compared up to the shorter run, the
-    # signatures in full.
+    # 1/(beta_1 ... beta_{k-1}) (beta_1 ~ sqrt(2/n) on a star; an FP32
+    # emulation of the same recurrence on star(2000) gives beta_3 up to 5e-4),
+    # so the GPU may carry on past the FP64 stopping step into directions whose
+    # Gauss weights are O(beta_k^2).  Coefficients are compared up to the
+    # shorter run, the signatures in full.
     for p in range(nv):
         k = int(min(gpu["steps"][p], ora["steps"][p]))
         np.testing.assert_allclose(gpu["alpha"][p, :k], ora["alpha"][p, :k], rtol=1e-5, atol=1e-5)
         np.testing.assert_allclose(gpu["beta"][p, :k - 1], ora["beta"][p, :k - 1], rtol=1e-5, atol=1e-5)
         if gpu["steps"][p] > ora["steps"][p]:
-            assert gpu["beta"][p, k - 1] < 1e-4
+            assert gpu["beta"][p, k - 1] < 5e-3
     assert_signature_parity(gpu, ora, csr.n, case)
     np.testing.assert_allclose(gpu["tau2"].sum(axis=1), 1.0, atol=1e-9)
+
+
+@pytest.mark.parametrize("heavy_min,piece", [(32, 64), (256, 512), (64, 1024), (100000, 64)])
+def test_row_schedules(heavy_min, piece):
+    # every schedule computes the same recurrence; heavy rows with partial
+    # pieces, rows just below / above the threshold, no heavy rows at all
+    header(f"schedule heavy_min={heavy_min} piece={piece}")
+    csr = inputs.chung_lu(10_000, 50_000, 2.5, seed=4)
+    rp, ci = S.to_device(csr)
+    g = S.build_graph(rp, ci)
+    g.set_schedule(heavy_min, piece)
+    sch = g.schedule()
+    deg = np.diff(csr.row_ptr)
+    heavy = deg >= heavy_min
+    assert sch["n_heavy"] == int(heavy.sum())
+    assert sch["n_pieces"] == int(((deg[heavy] + piece - 1) // piece).sum())
+    a, b, s = S.lanczos(g, 24, 15, 31)
+    th, w2 = S.ritz(a, b, s)
+    tt = torch.from_numpy(T256).cuda()
+    gpu = dict(heat=S.signature(th, w2, csr.n, tt).cpu().numpy(),
+               wave=S.signature(th, w2, csr.n, tt, S.SLAQ_SIG_WAVE).cpu().numpy(),
+               vnge=float(S.vnge(g, th, w2).cpu().numpy()[0]))
+    ora = oracle_run(csr, 24, 15, 31, T256)
+    np.testing.assert_allclose(a.cpu().numpy(), ora["alpha"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(b.cpu().numpy(), ora["beta"], rtol=1e-5, atol=1e-6)
+    assert_signature_parity(gpu, ora, csr.n, f"schedule {heavy_min}/{piece}")
 
 
 def test_weighted_graph():
