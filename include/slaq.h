@@ -157,6 +157,47 @@ slaq_status slaq_signature(const double* theta, const double* tau2, int nv, int 
 slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, int nv,
                       int m, double* out, void* stream);
 
+/* ---- Batched SLQ over many small graphs --------------------------------
+ * A batch is the block-diagonal union of G graphs: node_off[g] .. node_off[g+1]
+ * are graph g's nodes, row_ptr / col_idx its CSR rows with GLOBAL column ids
+ * (each row's columns lie inside its own graph).  Graph g uses the probes of
+ * slaq_lanczos with seed + g on that graph alone (keys are graph-local node
+ * ids), so each output row equals the plain path on the graph by itself, up
+ * to summation order.  Normalized Laplacian; n_g <= 8192, nv <= 256.
+ *
+ * slaq_batch_plan (host): node_off and nnz_off are HOST copies of the node
+ * offsets and of row_ptr at the graph starts (G+1 entries each);
+ * node_off_dev / row_ptr / col_idx are the device arrays, which must stay
+ * valid until slaq_batch_destroy.  Graphs are bucketed by node count
+ * (<= 64, 128, 256, ...); bucket_blocks (optional, n_buckets_cfg entries)
+ * overrides each bucket's workgroup size.  The plan owns a small device
+ * buffer (graph order and work counters).
+ *
+ * slaq_batch_run enqueues one persistent launch per bucket on `stream`; each
+ * workgroup pulls graphs, most expensive first, and computes degrees, probes,
+ * m Lanczos steps, the FP64 Gauss rule and the requested outputs (any may be
+ * NULL): heat double[G][nt] (n_g/nv sum tau2 exp(-t theta)), vnge double[G],
+ * alpha, beta, theta, tau2 double[G][nv][m], steps int32[G][nv].  With
+ * SLAQ_BATCH_GRAPH the launches are captured once into a hipGraph and
+ * replayed (re-captured when a buffer pointer or the seed changes).
+ *
+ * slaq_batch_autotune times every workgroup size in {128, 256, 512, 1024}
+ * per bucket (median of reps runs, HIP events) and keeps the fastest; the
+ * chosen sizes are returned in blocks_out[n_buckets] (optional). */
+enum { SLAQ_BATCH_GRAPH = 1u };
+typedef struct slaq_batch_s* slaq_batch_t;
+slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
+                            const int64_t* node_off_dev, const int64_t* row_ptr,
+                            const int32_t* col_idx, int nv, int m, int nt,
+                            const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out);
+slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* blocks, int* graphs);
+slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, double* heat, double* vnge,
+                           double* alpha, double* beta, int32_t* steps, double* theta, double* tau2,
+                           unsigned flags, void* stream);
+slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, double* vnge, int reps,
+                                int* blocks_out, float* best_ms_out, void* stream);
+slaq_status slaq_batch_destroy(slaq_batch_t b);
+
 /* Stage timing with HIP events (off by default).  While enabled, every launch
  * of a stage kernel ("spmm_chunks", "spmm_rows", "finalize", "update",
  * "batch_slq", "mlp_*") is bracketed by two events on its stream.

@@ -1,0 +1,667 @@
+// Batched SLQ for many small graphs (paper §3.1 and Algorithm 1 applied to
+// every graph of a collection): one workgroup computes one whole graph - degrees,
+// probes, m Lanczos steps, the FP64 Gauss rule and the heat trace / VNGE -
+// with the current Lanczos vector in LDS and the previous one and w in
+// registers.  Graphs are grouped into size buckets; each bucket is one
+// persistent launch whose workgroups pull graphs (largest first) from an
+// atomic queue.  All bucket launches of a run are replayed from one hipGraph.
+//
+// Probe p of graph g is the plain path's probe p for seed + g on that graph
+// alone (SplitMix64 keyed on the graph-local node id), so a graph's batched
+// result equals slaq_lanczos/slaq_signature on it, up to summation order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "common.hpp"
+#include "profile.hpp"
+#include "tridiag.hpp"
+
+namespace slaq {
+
+constexpr double kBatchEpsBreakdown = 1e-6;
+
+__device__ __forceinline__ uint64_t bmix64(uint64_t seed, uint64_t counter) {
+    uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct BatchArgs {
+    const int32_t* order;   // graph ids of this bucket, most expensive first
+    int count;              // graphs in this bucket
+    int* queue;             // work counter of this bucket (reset before launch)
+    const int64_t* goff;    // node offsets [G+1] (device)
+    const int64_t* rp;      // global row_ptr (device)
+    const int32_t* col;     // global column ids (device)
+    int nv, m, nt, n_max;
+    uint64_t seed;
+    const double* t;        // [nt]
+    double* heat;           // [G][nt] or NULL
+    double* vnge;           // [G] or NULL
+    double* alpha;          // [G][nv][m] or NULL
+    double* beta;           // [G][nv][m] or NULL
+    int32_t* steps;         // [G][nv] or NULL
+    double* theta;          // [G][nv][m] or NULL
+    double* tau2;           // [G][nv][m] or NULL
+};
+
+// LDS layout (bytes), n_max nodes, ld = 4F floats per node
+struct BatchLds {
+    size_t r, dinv, al, be, th, w2, ee, st, red, coef, total;
+};
+
+__host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int m, int B) {
+    const int F = (nv + 3) / 4;
+    BatchLds L{};
+    size_t off = 0;
+    L.r = off;
+    off += (size_t)n_max * F * 16;
+    L.dinv = off;
+    off += ((size_t)n_max * 4 + 15) / 16 * 16;
+    L.al = off;
+    off += (size_t)nv * m * 8;
+    L.be = off;
+    off += (size_t)nv * m * 8;
+    L.th = off;
+    off += (size_t)nv * m * 8;
+    L.w2 = off;
+    off += (size_t)nv * m * 8;
+    L.ee = off;
+    off += (size_t)nv * m * 8;
+    L.st = off;  // per probe: sigma, tau, a, active, steps (doubles)
+    off += (size_t)nv * 40;
+    L.red = off;
+    off += (size_t)B * 4 * 8;
+    L.coef = off;  // float sigma[4F], tau[4F], a[4F]
+    off += (size_t)3 * 4 * F * 4;
+    L.total = (off + 15) / 16 * 16;
+    return L;
+}
+
+template <int B, int IPT>
+__global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int F = (a.nv + 3) / 4;
+    const int ldq = F;  // quads per node
+    const BatchLds L = batch_lds(a.n_max, a.nv, a.m, B);
+    float4* R = (float4*)(lds + L.r);
+    float* dinv = (float*)(lds + L.dinv);
+    double* al = (double*)(lds + L.al);
+    double* be = (double*)(lds + L.be);
+    double* th = (double*)(lds + L.th);
+    double* w2 = (double*)(lds + L.w2);
+    double* ee = (double*)(lds + L.ee);
+    double* pst = (double*)(lds + L.st);  // [nv][5]: sigma, tau, a, active, steps
+    double* red = (double*)(lds + L.red);
+    float* coef = (float*)(lds + L.coef);  // [3][4F]
+    __shared__ int s_job;
+    __shared__ double s_scal[4];
+
+    const int t = threadIdx.x;
+    const int bact = (B / F) * F;  // threads with a fixed quad
+    const bool tact = t < bact;
+    const int q = t % F;
+    const int row0 = t / F;
+    const int rstride = bact / F;
+
+    for (;;) {
+        if (t == 0) s_job = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int job = s_job;
+        if (job >= a.count) break;
+        const int g = a.order[job];
+        const int64_t base = a.goff[g];
+        const int n = (int)(a.goff[g + 1] - base);
+        const int64_t* rp = a.rp + base;
+        const int32_t* col = a.col;
+
+        // ---- degrees, D^-1/2, tr L (non-isolated count) ---------------------
+        int nonzero = 0;
+        for (int i = t; i < n; i += B) {
+            const int64_t d = rp[i + 1] - rp[i];
+            dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
+            nonzero += d > 0 ? 1 : 0;
+        }
+        red[t] = (double)nonzero;
+        // ---- probes R_1 = v (graph-local ids, seed + g) ----------------------
+        const uint64_t sg = a.seed + (uint64_t)g;
+        for (int x = t; x < n * F; x += B) {
+            const int i = x / F, qq = x % F, p0 = 4 * qq;
+            const uint64_t z = bmix64(sg, 64ull * (uint64_t)i + (uint64_t)(p0 >> 6));
+            float v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -1.0f : 1.0f) : 0.0f;
+            R[x] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        const double sigma1 = 1.0 / sqrt((double)n);
+        for (int p = t; p < 4 * F; p += B) {
+            const bool on = p < a.nv;
+            coef[p] = on ? (float)sigma1 : 0.0f;
+            coef[4 * F + p] = 0.0f;
+            coef[8 * F + p] = 0.0f;
+            if (on) {
+                pst[5 * p + 0] = sigma1;
+                pst[5 * p + 1] = 0.0;
+                pst[5 * p + 2] = 0.0;
+                pst[5 * p + 3] = 1.0;
+                pst[5 * p + 4] = (double)a.m;
+            }
+        }
+        for (int k = t; k < a.nv * a.m; k += B) {
+            al[k] = 0.0;
+            be[k] = 0.0;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double s = 0.0;
+            for (int i = 0; i < B; ++i) s += red[i];
+            s_scal[0] = s;  // tr L of the normalized Laplacian
+        }
+        __syncthreads();
+
+        float4 prev[IPT], wv[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) prev[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+        for (int j = 1; j <= a.m; ++j) {
+            // ---- w = sigma L R_j - tau R_{j-1}; partial R_j . w -----------------
+            const float4 sgm = make_float4(coef[4 * q], coef[4 * q + 1], coef[4 * q + 2], coef[4 * q + 3]);
+            const float4 tau = make_float4(coef[4 * F + 4 * q], coef[4 * F + 4 * q + 1], coef[4 * F + 4 * q + 2],
+                                           coef[4 * F + 4 * q + 3]);
+            double s1[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const int i = row0 + k * rstride;
+                wv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (!tact || i >= n) continue;
+                const int64_t s = rp[i], e = rp[i + 1];
+                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int64_t kk = s; kk < e; ++kk) {
+                    const int c = (int)(col[kk] - base);
+                    if ((unsigned)c >= (unsigned)n) continue;  // column outside the graph: ignored
+                    const float dc = dinv[c];
+                    const float4 x = R[c * ldq + q];
+                    acc.x = fmaf(dc, x.x, acc.x);
+                    acc.y = fmaf(dc, x.y, acc.y);
+                    acc.z = fmaf(dc, x.z, acc.z);
+                    acc.w = fmaf(dc, x.w, acc.w);
+                }
+                const float di = dinv[i];
+                const float nz = e > s ? 1.0f : 0.0f;
+                const float4 ri = R[i * ldq + q];
+                float4 w;
+                w.x = fmaf(-tau.x, prev[k].x, sgm.x * fmaf(-di, acc.x, nz * ri.x));
+                w.y = fmaf(-tau.y, prev[k].y, sgm.y * fmaf(-di, acc.y, nz * ri.y));
+                w.z = fmaf(-tau.z, prev[k].z, sgm.z * fmaf(-di, acc.z, nz * ri.z));
+                w.w = fmaf(-tau.w, prev[k].w, sgm.w * fmaf(-di, acc.w, nz * ri.w));
+                wv[k] = w;
+                s1[0] = fma((double)ri.x, (double)w.x, s1[0]);
+                s1[1] = fma((double)ri.y, (double)w.y, s1[1]);
+                s1[2] = fma((double)ri.z, (double)w.z, s1[2]);
+                s1[3] = fma((double)ri.w, (double)w.w, s1[3]);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[4 * t + c] = s1[c];
+            __syncthreads();
+            if (t < a.nv) {
+                const int qq = t >> 2, cc = t & 3;
+                double s = 0.0;
+                for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
+                if (pst[5 * t + 3] != 0.0) {
+                    const double alpha = pst[5 * t + 0] * s;
+                    al[t * a.m + j - 1] = alpha;
+                    pst[5 * t + 2] = alpha * pst[5 * t + 0];
+                    coef[8 * F + t] = (float)pst[5 * t + 2];
+                } else {
+                    coef[8 * F + t] = 0.0f;
+                }
+            }
+            __syncthreads();
+            // ---- R_{j+1} = w - a R_j (in place); partial ||R_{j+1}||^2 ---------
+            const float4 av = make_float4(coef[8 * F + 4 * q], coef[8 * F + 4 * q + 1], coef[8 * F + 4 * q + 2],
+                                          coef[8 * F + 4 * q + 3]);
+            double s2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const int i = row0 + k * rstride;
+                if (!tact || i >= n) continue;
+                const float4 ri = R[i * ldq + q];
+                float4 r;
+                r.x = fmaf(-av.x, ri.x, wv[k].x);
+                r.y = fmaf(-av.y, ri.y, wv[k].y);
+                r.z = fmaf(-av.z, ri.z, wv[k].z);
+                r.w = fmaf(-av.w, ri.w, wv[k].w);
+                prev[k] = ri;
+                R[i * ldq + q] = r;
+                s2[0] = fma((double)r.x, (double)r.x, s2[0]);
+                s2[1] = fma((double)r.y, (double)r.y, s2[1]);
+                s2[2] = fma((double)r.z, (double)r.z, s2[2]);
+                s2[3] = fma((double)r.w, (double)r.w, s2[3]);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[4 * t + c] = s2[c];
+            __syncthreads();
+            if (t < a.nv) {
+                const int qq = t >> 2, cc = t & 3;
+                double s = 0.0;
+                for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
+                if (pst[5 * t + 3] != 0.0) {
+                    const double b = sqrt(fmax(s, 0.0));
+                    be[t * a.m + j - 1] = b;
+                    if (j < a.m && !(b > kBatchEpsBreakdown * 2.0)) {
+                        pst[5 * t + 3] = 0.0;
+                        pst[5 * t + 1] = 0.0;
+                        pst[5 * t + 0] = 0.0;
+                        coef[t] = 0.0f;
+                        coef[4 * F + t] = 0.0f;
+                        coef[8 * F + t] = 0.0f;
+                        pst[5 * t + 4] = (double)j;
+                    } else {
+                        const double tn = b * pst[5 * t + 0];
+                        pst[5 * t + 1] = tn;
+                        pst[5 * t + 0] = 1.0 / b;
+                        coef[t] = (float)(1.0 / b);
+                        coef[4 * F + t] = (float)tn;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- Gauss rule per probe (FP64 QR on T_p) --------------------------
+        if (t < a.nv) {
+            const int k = (int)pst[5 * t + 4];
+            double* d = th + t * a.m;
+            double* u = w2 + t * a.m;
+            double* e = ee + t * a.m;
+            for (int i = 0; i < k; ++i) {
+                d[i] = al[t * a.m + i];
+                e[i] = i + 1 < k ? be[t * a.m + i] : 0.0;
+            }
+            tridiag_eig_first_row(d, e, u, k, 1);
+            for (int i = 0; i < k; ++i) u[i] = u[i] * u[i];
+            for (int i = k; i < a.m; ++i) {
+                d[i] = 0.0;
+                u[i] = 0.0;
+            }
+            if (a.steps) a.steps[(int64_t)g * a.nv + t] = k;
+        }
+        __syncthreads();
+        // ---- outputs ---------------------------------------------------------
+        const double scale = (double)n / (double)a.nv;
+        const int cnt = a.nv * a.m;
+        if (a.heat) {
+            for (int b = t; b < a.nt; b += B) {
+                const double tt = a.t[b];
+                double s = 0.0;
+                for (int i = 0; i < cnt; ++i) s += w2[i] * exp(-tt * th[i]);
+                a.heat[(int64_t)g * a.nt + b] = scale * s;
+            }
+        }
+        if (a.alpha || a.theta) {
+            for (int i = t; i < cnt; i += B) {
+                if (a.alpha) a.alpha[(int64_t)g * cnt + i] = al[i];
+                if (a.beta) a.beta[(int64_t)g * cnt + i] = be[i];
+                if (a.theta) a.theta[(int64_t)g * cnt + i] = th[i];
+                if (a.tau2) a.tau2[(int64_t)g * cnt + i] = w2[i];
+            }
+        }
+        if (a.vnge) {
+            const double c = s_scal[0];
+            double s = 0.0;
+            if (c > 0.0)
+                for (int i = t; i < cnt; i += B) {
+                    const double x = th[i] / c;
+                    if (x > 0.0) s += w2[i] * (x * log(x));
+                }
+            red[t] = s;
+            __syncthreads();
+            if (t == 0) {
+                double tot = 0.0;
+                for (int i = 0; i < B; ++i) tot += red[i];
+                a.vnge[g] = -scale * tot;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_queues(int* q, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) q[i] = 0;
+}
+
+// ------------------------------------------------------------- host plan --
+struct BucketCfg {
+    int n_lo, n_hi;   // graphs with n in (n_lo, n_hi]
+    int block;        // threads per workgroup
+    int ipt;          // items per thread (ceil(n_hi*F / active threads))
+    int grid;         // persistent workgroups
+    size_t lds;
+};
+
+typedef void (*BatchKernel)(BatchArgs);
+
+static BatchKernel pick_kernel(int block, int ipt) {
+#define SLAQ_BK(Bv, Iv) if (block == Bv && ipt <= Iv) return batch_slq<Bv, Iv>;
+    SLAQ_BK(128, 1) SLAQ_BK(128, 2) SLAQ_BK(128, 3) SLAQ_BK(128, 4) SLAQ_BK(128, 6) SLAQ_BK(128, 8)
+    SLAQ_BK(128, 12) SLAQ_BK(128, 16) SLAQ_BK(128, 24) SLAQ_BK(128, 32)
+    SLAQ_BK(256, 1) SLAQ_BK(256, 2) SLAQ_BK(256, 3) SLAQ_BK(256, 4) SLAQ_BK(256, 6) SLAQ_BK(256, 8)
+    SLAQ_BK(256, 12) SLAQ_BK(256, 16)
+    SLAQ_BK(512, 1) SLAQ_BK(512, 2) SLAQ_BK(512, 3) SLAQ_BK(512, 4) SLAQ_BK(512, 6) SLAQ_BK(512, 8)
+    SLAQ_BK(1024, 1) SLAQ_BK(1024, 2) SLAQ_BK(1024, 3) SLAQ_BK(1024, 4)
+#undef SLAQ_BK
+    return nullptr;
+}
+
+}  // namespace slaq
+
+struct slaq_batch_s {
+    int64_t G;
+    int nv, m, nt;
+    const int64_t* goff;  // device
+    const int64_t* rp;    // device
+    const int32_t* col;   // device
+    std::vector<slaq::BucketCfg> buckets;
+    std::vector<int> bucket_start;  // offset into order per bucket
+    int32_t* order_dev;             // library-owned
+    int* queues_dev;                // library-owned, one counter per bucket
+    std::vector<std::vector<int32_t>> order_host;
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    const void* exec_key[8];
+    uint64_t exec_seed;
+};
+
+namespace slaq {
+
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return cus > 0 ? cus : 256;
+}
+
+static slaq_status configure_bucket(BucketCfg& b, int nv, int m, int block) {
+    const int F = (nv + 3) / 4;
+    const int bact = (block / F) * F;
+    SLAQ_REQUIRE(bact >= F && bact >= nv, SLAQ_ERR_UNSUPPORTED, "block %d too small for nv=%d", block, nv);
+    const int rows_per_pass = bact / F;
+    const int ipt = (b.n_hi + rows_per_pass - 1) / rows_per_pass;
+    static const int sizes[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+    int ipt_r = 0;
+    for (int v : sizes)
+        if (v >= ipt && pick_kernel(block, v)) {
+            ipt_r = v;
+            break;
+        }
+    SLAQ_REQUIRE(ipt_r > 0 && pick_kernel(block, ipt_r), SLAQ_ERR_UNSUPPORTED,
+                 "no batched kernel for block %d, %d rows per thread (n up to %d)", block, ipt_r, b.n_hi);
+    b.block = block;
+    b.ipt = ipt_r;
+    b.lds = batch_lds(b.n_hi, nv, m, block).total;
+    SLAQ_REQUIRE(b.lds <= 160 * 1024, SLAQ_ERR_UNSUPPORTED, "graphs of %d nodes need %zu bytes of LDS", b.n_hi, b.lds);
+    BatchKernel k = pick_kernel(block, ipt_r);
+    int per_cu = 0;
+    if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds) != hipSuccess)
+        per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, b.lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    b.grid = device_cus() * per_cu;
+    return SLAQ_OK;
+}
+
+}  // namespace slaq
+
+using namespace slaq;
+
+extern "C" {
+
+slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
+                            const int64_t* node_off_dev, const int64_t* row_ptr, const int32_t* col_idx, int nv,
+                            int m, int nt, const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out) {
+    clear_error();
+    SLAQ_REQUIRE(out, SLAQ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    SLAQ_REQUIRE(n_graphs >= 1 && node_off && nnz_off && node_off_dev && row_ptr && col_idx, SLAQ_ERR_INVALID_ARG,
+                 "need n_graphs >= 1 and non-NULL offsets / CSR");
+    SLAQ_REQUIRE(nv >= 1 && nv <= 256, SLAQ_ERR_INVALID_ARG, "batched nv must be in [1, 256]");
+    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
+    SLAQ_REQUIRE(nt >= 0, SLAQ_ERR_INVALID_ARG, "nt must be >= 0");
+    // size buckets by node count: (0,64], (64,128], (128,256], (256,512], ... up to the batch maximum
+    int64_t nmax = 0;
+    for (int64_t g = 0; g < n_graphs; ++g) {
+        const int64_t n = node_off[g + 1] - node_off[g];
+        SLAQ_REQUIRE(n >= 1, SLAQ_ERR_INVALID_ARG, "graph %lld has no nodes", (long long)g);
+        SLAQ_REQUIRE(nnz_off[g + 1] >= nnz_off[g], SLAQ_ERR_INVALID_ARG, "nnz offsets decrease at %lld", (long long)g);
+        nmax = std::max(nmax, n);
+    }
+    SLAQ_REQUIRE(nmax <= 8192, SLAQ_ERR_UNSUPPORTED, "batched graphs are limited to 8192 nodes (got %lld)",
+                 (long long)nmax);
+    std::vector<int> edges = {0, 64};
+    while (edges.back() < nmax) edges.push_back(edges.back() * 2);
+    slaq_batch_s* b = new (std::nothrow) slaq_batch_s();
+    SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "out of host memory");
+    b->G = n_graphs;
+    b->nv = nv;
+    b->m = m;
+    b->nt = nt;
+    b->goff = node_off_dev;
+    b->rp = row_ptr;
+    b->col = col_idx;
+    const int nb = (int)edges.size() - 1;
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> members(nb);
+    for (int64_t g = 0; g < n_graphs; ++g) {
+        const int64_t n = node_off[g + 1] - node_off[g];
+        int k = 0;
+        while (n > edges[k + 1]) ++k;
+        // cost ~ nnz * nv * m + n * nt (gathers, quadrature)
+        members[k].push_back({(nnz_off[g + 1] - nnz_off[g]) + n, (int32_t)g});
+    }
+    std::vector<int32_t> order;
+    for (int k = 0; k < nb; ++k) {
+        if (members[k].empty()) continue;
+        std::stable_sort(members[k].begin(), members[k].end(),
+                         [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                             return x.first > y.first;
+                         });
+        BucketCfg c{};
+        c.n_lo = edges[k];
+        c.n_hi = std::min<int64_t>(edges[k + 1], nmax);
+        int64_t top = 0;
+        for (auto& pr : members[k]) top = std::max<int64_t>(top, node_off[pr.second + 1] - node_off[pr.second]);
+        c.n_hi = (int)top;
+        const int bidx = (int)b->buckets.size();
+        int block = c.n_hi <= 64 ? 128 : (c.n_hi <= 256 ? 256 : 512);
+        if (bucket_blocks && bidx < n_buckets_cfg && bucket_blocks[bidx] > 0) block = bucket_blocks[bidx];
+        slaq_status s = configure_bucket(c, nv, m, block);
+        if (s != SLAQ_OK) {
+            delete b;
+            return s;
+        }
+        b->bucket_start.push_back((int)order.size());
+        std::vector<int32_t> ids;
+        for (auto& pr : members[k]) {
+            order.push_back(pr.second);
+            ids.push_back(pr.second);
+        }
+        b->order_host.push_back(ids);
+        b->buckets.push_back(c);
+    }
+    b->bucket_start.push_back((int)order.size());
+    if (hipMalloc(&b->order_dev, order.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&b->queues_dev, b->buckets.size() * sizeof(int)) != hipSuccess) {
+        delete b;
+        set_error("hipMalloc of the batch plan failed");
+        return SLAQ_ERR_HIP;
+    }
+    if (hipMemcpy(b->order_dev, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(b->order_dev);
+        hipFree(b->queues_dev);
+        delete b;
+        set_error("copy of the batch order failed");
+        return SLAQ_ERR_HIP;
+    }
+    *out = b;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* blocks, int* graphs) {
+    clear_error();
+    SLAQ_REQUIRE(b && n_buckets, SLAQ_ERR_INVALID_ARG, "NULL argument");
+    *n_buckets = (int)b->buckets.size();
+    for (size_t k = 0; k < b->buckets.size(); ++k) {
+        if (n_hi) n_hi[k] = b->buckets[k].n_hi;
+        if (blocks) blocks[k] = b->buckets[k].block;
+        if (graphs) graphs[k] = b->bucket_start[k + 1] - b->bucket_start[k];
+    }
+    return SLAQ_OK;
+}
+
+static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t, double* heat, double* vnge,
+                                 double* alpha, double* beta, int32_t* steps, double* theta, double* tau2,
+                                 hipStream_t st, int only_bucket) {
+    const int nbk = (int)b->buckets.size();
+    hipLaunchKernelGGL(reset_queues, dim3(1), dim3(64), 0, st, b->queues_dev, nbk);
+    SLAQ_LAUNCHED();
+    for (int k = 0; k < nbk; ++k) {
+        if (only_bucket >= 0 && k != only_bucket) continue;
+        const BucketCfg& c = b->buckets[k];
+        BatchArgs a{};
+        a.order = b->order_dev + b->bucket_start[k];
+        a.count = b->bucket_start[k + 1] - b->bucket_start[k];
+        a.queue = b->queues_dev + k;
+        a.goff = b->goff;
+        a.rp = b->rp;
+        a.col = b->col;
+        a.nv = b->nv;
+        a.m = b->m;
+        a.nt = b->nt;
+        a.n_max = c.n_hi;
+        a.seed = seed;
+        a.t = t;
+        a.heat = heat;
+        a.vnge = vnge;
+        a.alpha = alpha;
+        a.beta = beta;
+        a.steps = steps;
+        a.theta = theta;
+        a.tau2 = tau2;
+        BatchKernel kern = pick_kernel(c.block, c.ipt);
+        const int grid = std::min(c.grid, a.count);
+        SLAQ_TIMED("batch_slq", st, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a));
+        SLAQ_LAUNCHED();
+    }
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, double* heat, double* vnge, double* alpha,
+                           double* beta, int32_t* steps, double* theta, double* tau2, unsigned flags, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
+    SLAQ_REQUIRE(!heat || (t && b->nt > 0), SLAQ_ERR_INVALID_ARG, "heat needs the time grid t (nt > 0)");
+    SLAQ_REQUIRE((!beta || alpha) && (!tau2 || theta), SLAQ_ERR_INVALID_ARG, "beta needs alpha, tau2 needs theta");
+    hipStream_t st = (hipStream_t)stream;
+    if (!(flags & SLAQ_BATCH_GRAPH)) return enqueue_batch(b, seed, t, heat, vnge, alpha, beta, steps, theta, tau2, st, -1);
+    // replay one captured hipGraph; (re)capture when the buffers or the seed change
+    const void* key[8] = {t, heat, vnge, alpha, beta, steps, theta, tau2};
+    const bool same = b->exec && std::memcmp(key, b->exec_key, sizeof(key)) == 0 && b->exec_seed == seed;
+    if (!same) {
+        if (b->exec) {
+            hipGraphExecDestroy(b->exec);
+            hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+        }
+        SLAQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        slaq_status s = enqueue_batch(b, seed, t, heat, vnge, alpha, beta, steps, theta, tau2, st, -1);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &gr);
+        SLAQ_REQUIRE(s == SLAQ_OK, s, "%s", slaq_last_error());
+        SLAQ_HIP(e);
+        SLAQ_HIP(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0));
+        b->graph = gr;
+        std::memcpy(b->exec_key, key, sizeof(key));
+        b->exec_seed = seed;
+    }
+    SLAQ_HIP(hipGraphLaunch(b->exec, st));
+    return SLAQ_OK;
+}
+
+// Host autotuner: for every bucket, time each candidate block size (HIP events,
+// median of `reps` runs of that bucket alone) and keep the fastest.  Writes the
+// chosen block per bucket to blocks_out (n_buckets entries) when non-NULL.
+slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, double* vnge, int reps,
+                                int* blocks_out, float* best_ms_out, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
+    SLAQ_REQUIRE(reps >= 1 && reps <= 100, SLAQ_ERR_INVALID_ARG, "reps must be in [1, 100]");
+    hipStream_t st = (hipStream_t)stream;
+    const int cand[4] = {128, 256, 512, 1024};
+    hipEvent_t e0, e1;
+    SLAQ_HIP(hipEventCreate(&e0));
+    SLAQ_HIP(hipEventCreate(&e1));
+    for (size_t k = 0; k < b->buckets.size(); ++k) {
+        BucketCfg best = b->buckets[k];
+        float best_ms = 1e30f;
+        for (int ci = 0; ci < 4; ++ci) {
+            BucketCfg c = b->buckets[k];
+            if (configure_bucket(c, b->nv, b->m, cand[ci]) != SLAQ_OK) continue;
+            const BucketCfg keep = b->buckets[k];
+            b->buckets[k] = c;
+            std::vector<float> ts;
+            for (int r = 0; r < reps; ++r) {
+                SLAQ_HIP(hipEventRecord(e0, st));
+                slaq_status s = enqueue_batch(b, 12345, t, heat, vnge, nullptr, nullptr, nullptr, nullptr, nullptr, st,
+                                              (int)k);
+                if (s != SLAQ_OK) {
+                    b->buckets[k] = keep;
+                    return s;
+                }
+                SLAQ_HIP(hipEventRecord(e1, st));
+                SLAQ_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                SLAQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ts.push_back(ms);
+            }
+            std::sort(ts.begin(), ts.end());
+            const float med = ts[ts.size() / 2];
+            if (med < best_ms) {
+                best_ms = med;
+                best = c;
+            }
+            b->buckets[k] = keep;
+        }
+        b->buckets[k] = best;
+        if (blocks_out) blocks_out[k] = best.block;
+        if (best_ms_out) best_ms_out[k] = best_ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (b->exec) {  // schedule changed: drop the captured graph
+        hipGraphExecDestroy(b->exec);
+        hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+    }
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_destroy(slaq_batch_t b) {
+    if (!b) return SLAQ_OK;
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        hipGraphDestroy(b->graph);
+    }
+    hipFree(b->order_dev);
+    hipFree(b->queues_dev);
+    delete b;
+    return SLAQ_OK;
+}
+
+}  // extern "C"

@@ -44,6 +44,11 @@ SIGNATURES = {
     "slaq_ritz": [_vp, _vp, _vp, _int, _int, _vp, _vp, _vp],
     "slaq_signature": [_vp, _vp, _int, _int, _i64, _vp, _int, _int, _vp, _vp],
     "slaq_vnge": [_vp, _vp, _vp, _int, _int, _vp, _vp],
+    "slaq_batch_plan": [_i64, _vp, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _int, ctypes.POINTER(_vp)],
+    "slaq_batch_buckets": [_vp, ctypes.POINTER(_int), _vp, _vp, _vp],
+    "slaq_batch_run": [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
+    "slaq_batch_autotune": [_vp, _vp, _vp, _vp, _int, _vp, _vp, _vp],
+    "slaq_batch_destroy": [_vp],
     "slaq_profile_enable": [_int],
     "slaq_profile_reset": [],
     "slaq_profile_read": [ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
@@ -221,6 +226,91 @@ def vnge(g, theta, tau2, out=None, stream=None):
         out = torch.empty(1, dtype=torch.float64, device=theta.device)
     _check(lib().slaq_vnge(g.handle, _ptr(theta), _ptr(tau2), nv, m, _ptr(out), _stream(stream)))
     return out
+
+
+SLAQ_BATCH_GRAPH = 1
+
+
+class Batch:
+    """Plan of a batch of small graphs (slaq_batch_plan); keeps the device CSR
+    alive and owns the library plan."""
+
+    def __init__(self, handle, n_graphs, nv, m, nt, keep):
+        self.handle = handle
+        self.G = n_graphs
+        self.nv, self.m, self.nt = nv, m, nt
+        self._keep = keep
+
+    def buckets(self):
+        nb = _int()
+        _check(lib().slaq_batch_buckets(self.handle, ctypes.byref(nb), None, None, None))
+        k = nb.value
+        n_hi, blocks, graphs = (ctypes.c_int * k)(), (ctypes.c_int * k)(), (ctypes.c_int * k)()
+        _check(lib().slaq_batch_buckets(self.handle, ctypes.byref(nb), n_hi, blocks, graphs))
+        return [{"n_hi": n_hi[i], "block": blocks[i], "graphs": graphs[i]} for i in range(k)]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.slaq_batch_destroy(h)
+            self.handle = None
+
+
+def batch_plan(union_csr, node_off, nv, m, nt, bucket_blocks=None, device="cuda"):
+    """slaq_batch_plan for a block-diagonal union (inputs.disjoint_union)."""
+    import numpy as np
+    node_off = np.ascontiguousarray(node_off, dtype=np.int64)
+    nnz_off = np.ascontiguousarray(union_csr.row_ptr[node_off], dtype=np.int64)
+    rp = torch.from_numpy(union_csr.row_ptr).to(device)
+    ci = torch.from_numpy(union_csr.col_idx).to(device)
+    goff = torch.from_numpy(node_off).to(device)
+    G = len(node_off) - 1
+    bb = None
+    nbb = 0
+    if bucket_blocks is not None:
+        bb = (ctypes.c_int * len(bucket_blocks))(*bucket_blocks)
+        nbb = len(bucket_blocks)
+    h = _vp()
+    _check(lib().slaq_batch_plan(G, node_off.ctypes.data_as(_vp), nnz_off.ctypes.data_as(_vp), _ptr(goff),
+                                 _ptr(rp), _ptr(ci), nv, m, nt, bb, nbb, ctypes.byref(h)))
+    return Batch(h, G, nv, m, nt, {"rp": rp, "ci": ci, "goff": goff})
+
+
+def batch_run(b, seed, t=None, heat=True, vnge=True, ritz=False, coeffs=False, graph=False, out=None,
+              stream=None):
+    """slaq_batch_run -> dict of the requested outputs (device tensors)."""
+    dev = b._keep["rp"].device
+    o = dict(out or {})
+    f64 = torch.float64
+    if heat and "heat" not in o:
+        o["heat"] = torch.empty((b.G, b.nt), dtype=f64, device=dev)
+    if vnge and "vnge" not in o:
+        o["vnge"] = torch.empty(b.G, dtype=f64, device=dev)
+    if coeffs and "alpha" not in o:
+        o["alpha"] = torch.empty((b.G, b.nv, b.m), dtype=f64, device=dev)
+        o["beta"] = torch.empty((b.G, b.nv, b.m), dtype=f64, device=dev)
+        o["steps"] = torch.empty((b.G, b.nv), dtype=torch.int32, device=dev)
+    if ritz and "theta" not in o:
+        o["theta"] = torch.empty((b.G, b.nv, b.m), dtype=f64, device=dev)
+        o["tau2"] = torch.empty((b.G, b.nv, b.m), dtype=f64, device=dev)
+        o.setdefault("steps", torch.empty((b.G, b.nv), dtype=torch.int32, device=dev))
+    g = o.get
+    _check(lib().slaq_batch_run(b.handle, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(t), _ptr(g("heat")),
+                                _ptr(g("vnge")), _ptr(g("alpha")), _ptr(g("beta")), _ptr(g("steps")),
+                                _ptr(g("theta")), _ptr(g("tau2")), SLAQ_BATCH_GRAPH if graph else 0,
+                                _stream(stream)))
+    return o
+
+
+def batch_autotune(b, t, reps=3, stream=None):
+    """slaq_batch_autotune -> chosen workgroup size and time (ms) per bucket."""
+    dev = b._keep["rp"].device
+    heat = torch.empty((b.G, b.nt), dtype=torch.float64, device=dev)
+    vn = torch.empty(b.G, dtype=torch.float64, device=dev)
+    k = len(b.buckets())
+    blocks, ms = (ctypes.c_int * k)(), (ctypes.c_float * k)()
+    _check(lib().slaq_batch_autotune(b.handle, _ptr(t), _ptr(heat), _ptr(vn), reps, blocks, ms, _stream(stream)))
+    return [(blocks[i], ms[i]) for i in range(k)]
 
 
 def profile_enable(on=True):

@@ -1,0 +1,101 @@
+"""GPU parity of the batched engine: every graph of a batch against the FP64
+oracle run on that graph alone (seed + g), against the plain GPU path, and
+hipGraph replays against the eager launch."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import slq as O
+from paper_2003_01282_amd import inputs
+from paper_2003_01282_amd import slaq as S
+
+from gpu_helpers import TOL_HEAT_REL, TOL_VNGE_REL
+
+pytestmark = pytest.mark.gpu
+
+T = O.t_grid(256)
+
+
+def mixed_batch(count, seed):
+    gs = inputs.small_graph_mix(count, seed=seed)
+    # degenerate members: a single node, no edges, a complete graph, a star
+    gs[3] = inputs.CSR(n=1, row_ptr=np.zeros(2, dtype=np.int64), col_idx=np.zeros(0, dtype=np.int32))
+    gs[5] = inputs.CSR(n=9, row_ptr=np.zeros(10, dtype=np.int64), col_idx=np.zeros(0, dtype=np.int32))
+    gs[7] = inputs.complete(40)
+    gs[9] = inputs.star(300)
+    return gs
+
+
+@pytest.fixture(scope="module")
+def batch60():
+    gs = mixed_batch(60, seed=8)
+    union, off = inputs.disjoint_union(gs)
+    b = S.batch_plan(union, off, nv=20, m=10, nt=T.size)
+    t = torch.from_numpy(T).cuda()
+    out = S.batch_run(b, 1234, t, heat=True, vnge=True, coeffs=True, ritz=True)
+    torch.cuda.synchronize()
+    return gs, b, t, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_batched_against_oracle(batch60):
+    gs, b, t, out = batch60
+    print(f"\n[gpu] batched 60 graphs buckets {b.buckets()}", flush=True)
+    worst = 0.0
+    for g, csr in enumerate(gs):
+        og = O.build_graph(csr.n, csr.row_ptr, csr.col_idx)
+        a, be, st = O.lanczos(og, 20, 10, 1234 + g)
+        th, w2 = O.ritz(a, be, st)
+        heat = O.heat_trace(th, w2, csr.n, T)
+        H = O.vnge(th, w2, csr.n, og.trace)
+        rel = np.abs(out["heat"][g] - heat) / np.abs(heat)
+        worst = max(worst, rel.max())
+        assert rel.max() <= TOL_HEAT_REL, (g, rel.max())
+        if H != 0.0:
+            assert abs(out["vnge"][g] - H) <= TOL_VNGE_REL * abs(H), g
+        else:
+            assert abs(out["vnge"][g]) < 1e-12
+        k = np.minimum(out["steps"][g], st)
+        for p in range(20):
+            np.testing.assert_allclose(out["alpha"][g, p, :k[p]], a[p, :k[p]], rtol=1e-5, atol=1e-5)
+    print(f"worst heat rel {worst:.2e}")
+
+
+def test_batched_matches_plain_gpu_path(batch60):
+    gs, b, t, out = batch60
+    for g in (0, 1, 2, 7, 9, 20, 41):
+        csr = gs[g]
+        rp, ci = S.to_device(csr)
+        gr = S.build_graph(rp, ci)
+        a, be, st = S.lanczos(gr, 20, 10, 1234 + g)
+        th, w2 = S.ritz(a, be, st)
+        heat = S.signature(th, w2, csr.n, t).cpu().numpy()
+        np.testing.assert_allclose(out["heat"][g], heat, rtol=2e-5)
+
+
+def test_hipgraph_replays_match_eager(batch60):
+    gs, b, t, out = batch60
+    eager = S.batch_run(b, 99, t)
+    torch.cuda.synchronize()
+    ref = eager["heat"].cpu().numpy().copy()
+    outs = {"heat": torch.empty_like(eager["heat"]), "vnge": torch.empty_like(eager["vnge"])}
+    for r in range(4):
+        outs["heat"].fill_(-1.0)
+        S.batch_run(b, 99, t, graph=True, out=outs)
+        torch.cuda.synchronize()
+        assert np.array_equal(outs["heat"].cpu().numpy(), ref), r
+        # eager work between replays
+        x = torch.randn(1000, device="cuda")
+        (x * 2).sum().item()
+
+
+def test_autotune_keeps_results():
+    gs = inputs.small_graph_mix(200, seed=3)
+    union, off = inputs.disjoint_union(gs)
+    b = S.batch_plan(union, off, nv=20, m=10, nt=T.size)
+    t = torch.from_numpy(T).cuda()
+    before = S.batch_run(b, 5, t)["heat"].cpu().numpy()
+    choice = S.batch_autotune(b, t, reps=2)
+    print(f"\n[gpu] autotune {choice} buckets {b.buckets()}", flush=True)
+    assert all(c[0] in (128, 256, 512, 1024) for c in choice)
+    after = S.batch_run(b, 5, t)["heat"].cpu().numpy()
+    np.testing.assert_allclose(after, before, rtol=1e-6)
