@@ -376,6 +376,7 @@ struct slaq_batch_s {
     std::vector<std::vector<int32_t>> order_host;
     hipGraphExec_t exec;
     hipGraph_t graph;
+    hipStream_t cap;  // private stream used only for capture (the NULL stream cannot be captured)
     const void* exec_key[8];
     uint64_t exec_seed;
 };
@@ -579,10 +580,11 @@ slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, doubl
             hipGraphDestroy(b->graph);
             b->exec = nullptr;
         }
-        SLAQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        slaq_status s = enqueue_batch(b, seed, t, heat, vnge, alpha, beta, steps, theta, tau2, st, -1);
+        if (!b->cap) SLAQ_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        SLAQ_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        slaq_status s = enqueue_batch(b, seed, t, heat, vnge, alpha, beta, steps, theta, tau2, b->cap, -1);
         hipGraph_t gr = nullptr;
-        hipError_t e = hipStreamEndCapture(st, &gr);
+        hipError_t e = hipStreamEndCapture(b->cap, &gr);
         SLAQ_REQUIRE(s == SLAQ_OK, s, "%s", slaq_last_error());
         SLAQ_HIP(e);
         SLAQ_HIP(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0));
@@ -658,6 +660,7 @@ slaq_status slaq_batch_destroy(slaq_batch_t b) {
         hipGraphExecDestroy(b->exec);
         hipGraphDestroy(b->graph);
     }
+    if (b->cap) hipStreamDestroy(b->cap);
     hipFree(b->order_dev);
     hipFree(b->queues_dev);
     delete b;
