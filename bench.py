@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=20200302)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="copy this many MiB device-to-device once (calibrates hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -186,6 +188,14 @@ def main():
     ci = torch.from_numpy(csr.col_idx).to(dev)
     tgrid = torch.from_numpy(inputs.t_grid(256)).to(dev)
     nt = tgrid.numel()
+
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB device-to-device")
+        del src, dst
 
     # preallocated buffers: the timed step allocates nothing
     g0 = S.build_graph(rp, ci)

@@ -198,6 +198,58 @@ slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, d
                                 int* blocks_out, float* best_ms_out, void* stream);
 slaq_status slaq_batch_destroy(slaq_batch_t b);
 
+/* ---- Learned closure (an addition to the paper's method) ----------------
+ * An MLP d_in (<= 32, zero-padded to 32) -> hidden -> hidden -> hidden -> nt
+ * with SiLU activations, trained with MSE and Adam on FP32 master weights;
+ * every matrix product is a BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
+ * accumulation.  It maps a probe's mf-step Gauss rule (features: nodes
+ * ascending, then weights) to y(t) = log Q_30(t) - log Q_mf(t), where
+ * Q_m(t) = sum_k tau2_k exp(-t theta_k) is the probe's m-point Gauss value of
+ * exp(-tL) (§3.1, eq. "quadratic").  The handle owns its parameters (device
+ * memory, freed by slaq_closure_destroy); batch activations live in a
+ * caller workspace of slaq_closure_workspace() bytes.  Not thread-safe per
+ * handle.
+ *
+ * create: Glorot-uniform init from SplitMix64(seed); info: parameter count,
+ * offsets of W1 b1 W2 b2 W3 b3 W4 b4 in the FP32 parameter vector
+ * (W row-major d_in x d_out), layer widths.  get (which 0 = weights, 1 =
+ * gradients of the last train_step) / set copy that vector device-to-device.
+ * train_step: x BF16 [batch][32], y FP32 [batch][nt]; writes the gradients,
+ * the loss (device float, optional) and, when lr > 0, one Adam step.
+ * forward: y_hat FP32 [batch][nt].
+ * rules: from Lanczos coefficients (row stride ms, steps) the mf-node Gauss
+ * rule (theta, tau2 [count][mf], ascending) and the (mf+1)-node Gauss-Radau
+ * rule with a node at 0 (theta_r, tau2_r [count][mf+1]); for exp(-tx) they
+ * bracket the exact quadratic form from below and above.
+ * features: BF16 x [count][32] from an mf-node rule.
+ * gauss_values: Q[count][nt] from the first kn of ks nodes per probe.
+ * targets: y = log(q_hi) - log(q_lo) elementwise (FP32).
+ * apply: per probe Q_hat = q5 exp(y_hat) clamped to [q5, qr]; heat[g][t] =
+ * graph_n[g]/nv sum over the graph's nv probes; flags[g] = 1 when a raw
+ * prediction left the bracket by more than tol (relative) - such graphs are
+ * to be recomputed by plain SLQ. */
+typedef struct slaq_closure_s* slaq_closure_t;
+slaq_status slaq_closure_create(int d_in, int hidden, int nt, uint64_t seed, void* stream, slaq_closure_t* out);
+slaq_status slaq_closure_destroy(slaq_closure_t c);
+slaq_status slaq_closure_info(slaq_closure_t c, int64_t* n_params, int64_t* offsets, int* dims);
+slaq_status slaq_closure_workspace(slaq_closure_t c, int64_t batch, size_t* bytes);
+slaq_status slaq_closure_get(slaq_closure_t c, int which, float* dst, void* stream);
+slaq_status slaq_closure_set(slaq_closure_t c, const float* src, int reset_optimizer, void* stream);
+slaq_status slaq_closure_forward(slaq_closure_t c, const void* x, int64_t batch, float* yhat, void* workspace,
+                                 size_t ws_bytes, void* stream);
+slaq_status slaq_closure_train_step(slaq_closure_t c, const void* x, const float* y, int64_t batch, float lr,
+                                    float* loss, void* workspace, size_t ws_bytes, void* stream);
+slaq_status slaq_closure_rules(const double* alpha, const double* beta, const int32_t* steps, int64_t count,
+                               int ms, int mf, double* theta, double* tau2, double* theta_r, double* tau2_r,
+                               void* stream);
+slaq_status slaq_closure_features(const double* theta, const double* tau2, int64_t count, int mf, void* x,
+                                  void* stream);
+slaq_status slaq_closure_gauss_values(const double* theta, const double* tau2, int64_t count, int kn, int ks,
+                                      const double* t, int nt, double* Q, void* stream);
+slaq_status slaq_closure_targets(const double* q_hi, const double* q_lo, int64_t total, float* y, void* stream);
+slaq_status slaq_closure_apply(const float* yhat, const double* q5, const double* qr, int n_graphs, int nv, int nt,
+                               const int64_t* graph_n, double tol, double* heat, int* flags, void* stream);
+
 /* Stage timing with HIP events (off by default).  While enabled, every launch
  * of a stage kernel ("spmm_chunks", "spmm_rows", "finalize", "update",
  * "batch_slq", "mlp_*") is bracketed by two events on its stream.

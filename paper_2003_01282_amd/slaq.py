@@ -49,6 +49,19 @@ SIGNATURES = {
     "slaq_batch_run": [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
     "slaq_batch_autotune": [_vp, _vp, _vp, _vp, _int, _vp, _vp, _vp],
     "slaq_batch_destroy": [_vp],
+    "slaq_closure_create": [_int, _int, _int, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)],
+    "slaq_closure_destroy": [_vp],
+    "slaq_closure_info": [_vp, ctypes.POINTER(_i64), _vp, _vp],
+    "slaq_closure_workspace": [_vp, _i64, ctypes.POINTER(_sz)],
+    "slaq_closure_get": [_vp, _int, _vp, _vp],
+    "slaq_closure_set": [_vp, _vp, _int, _vp],
+    "slaq_closure_forward": [_vp, _vp, _i64, _vp, _vp, _sz, _vp],
+    "slaq_closure_train_step": [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _sz, _vp],
+    "slaq_closure_rules": [_vp, _vp, _vp, _i64, _int, _int, _vp, _vp, _vp, _vp, _vp],
+    "slaq_closure_features": [_vp, _vp, _i64, _int, _vp, _vp],
+    "slaq_closure_gauss_values": [_vp, _vp, _i64, _int, _int, _vp, _int, _vp, _vp],
+    "slaq_closure_targets": [_vp, _vp, _i64, _vp, _vp],
+    "slaq_closure_apply": [_vp, _vp, _vp, _int, _int, _int, _vp, ctypes.c_double, _vp, _vp, _vp],
     "slaq_profile_enable": [_int],
     "slaq_profile_reset": [],
     "slaq_profile_read": [ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
@@ -311,6 +324,124 @@ def batch_autotune(b, t, reps=3, stream=None):
     blocks, ms = (ctypes.c_int * k)(), (ctypes.c_float * k)()
     _check(lib().slaq_batch_autotune(b.handle, _ptr(t), _ptr(heat), _ptr(vn), reps, blocks, ms, _stream(stream)))
     return [(blocks[i], ms[i]) for i in range(k)]
+
+
+CLOSURE_DIN_PAD = 32
+
+
+class Closure:
+    """The learned closure network (slaq_closure_*); owns its parameters."""
+
+    def __init__(self, d_in=10, hidden=256, nt=256, seed=0, stream=None):
+        h = _vp()
+        _check(lib().slaq_closure_create(d_in, hidden, nt, ctypes.c_uint64(seed), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.d_in, self.hidden, self.nt = d_in, hidden, nt
+        P = _i64()
+        offs = (ctypes.c_int64 * 8)()
+        dims = (ctypes.c_int * 5)()
+        _check(lib().slaq_closure_info(h, ctypes.byref(P), offs, dims))
+        self.n_params = P.value
+        self.offsets = list(offs)
+        self.dims = list(dims)
+        self._ws = None
+
+    def _workspace(self, batch):
+        b = _sz()
+        _check(lib().slaq_closure_workspace(self.handle, batch, ctypes.byref(b)))
+        if self._ws is None or self._ws.numel() < b.value:
+            self._ws = _empty_aligned(b.value, "cuda")
+        return self._ws
+
+    def get(self, which=0, stream=None):
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().slaq_closure_get(self.handle, which, _ptr(out), _stream(stream)))
+        return out
+
+    def set(self, params, reset_optimizer=True, stream=None):
+        _dev(params, torch.float32, "params")
+        _check(lib().slaq_closure_set(self.handle, _ptr(params), 1 if reset_optimizer else 0, _stream(stream)))
+
+    def layers(self, vec=None):
+        """[(W, b)] views of a parameter vector (default: the weights)."""
+        v = self.get(0) if vec is None else vec
+        out = []
+        for l in range(4):
+            wo, bo = self.offsets[2 * l], self.offsets[2 * l + 1]
+            W = v[wo:bo].view(self.dims[l], self.dims[l + 1])
+            out.append((W, v[bo:bo + self.dims[l + 1]]))
+        return out
+
+    def train_step(self, x, y, lr, loss=None, stream=None):
+        _dev(x, torch.bfloat16, "x")
+        _dev(y, torch.float32, "y")
+        B = x.shape[0]
+        ws = self._workspace(B)
+        _check(lib().slaq_closure_train_step(self.handle, _ptr(x), _ptr(y), B, ctypes.c_float(lr), _ptr(loss),
+                                             _ptr(ws), ws.numel(), _stream(stream)))
+
+    def forward(self, x, out=None, stream=None):
+        _dev(x, torch.bfloat16, "x")
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty((B, self.nt), dtype=torch.float32, device="cuda")
+        ws = self._workspace(B)
+        _check(lib().slaq_closure_forward(self.handle, _ptr(x), B, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _LIB is not None:
+            _LIB.slaq_closure_destroy(h)
+            self.handle = None
+
+
+def closure_rules(alpha, beta, steps, mf=5, stream=None):
+    """mf-node Gauss rule and (mf+1)-node Gauss-Radau rule per probe, from
+    Lanczos coefficients of any length > mf (alpha/beta [..., ms])."""
+    ms = alpha.shape[-1]
+    count = alpha.numel() // ms
+    f = dict(dtype=torch.float64, device=alpha.device)
+    th, w2 = torch.empty((count, mf), **f), torch.empty((count, mf), **f)
+    thr, w2r = torch.empty((count, mf + 1), **f), torch.empty((count, mf + 1), **f)
+    _check(lib().slaq_closure_rules(_ptr(alpha), _ptr(beta), _ptr(steps), count, ms, mf, _ptr(th), _ptr(w2), _ptr(thr),
+                                    _ptr(w2r), _stream(stream)))
+    return th, w2, thr, w2r
+
+
+def closure_features(theta, tau2, stream=None):
+    count, mf = theta.shape
+    x = torch.empty((count, CLOSURE_DIN_PAD), dtype=torch.bfloat16, device=theta.device)
+    _check(lib().slaq_closure_features(_ptr(theta), _ptr(tau2), count, mf, _ptr(x), _stream(stream)))
+    return x
+
+
+def gauss_values(theta, tau2, t, kn=None, stream=None):
+    """Q[count][nt] = sum_k tau2 exp(-t theta) over the first kn nodes."""
+    ks = theta.shape[-1]
+    count = theta.numel() // ks
+    kn = ks if kn is None else kn
+    Q = torch.empty((count, t.numel()), dtype=torch.float64, device=theta.device)
+    _check(lib().slaq_closure_gauss_values(_ptr(theta), _ptr(tau2), count, kn, ks, _ptr(t), t.numel(), _ptr(Q),
+                                           _stream(stream)))
+    return Q
+
+
+def closure_targets(q_hi, q_lo, stream=None):
+    y = torch.empty(q_hi.shape, dtype=torch.float32, device=q_hi.device)
+    _check(lib().slaq_closure_targets(_ptr(q_hi), _ptr(q_lo), q_hi.numel(), _ptr(y), _stream(stream)))
+    return y
+
+
+def closure_apply(yhat, q5, qr, graph_n, nv, tol, stream=None):
+    """-> heat [G][nt] and flags [G] (1 = recompute with plain SLQ)."""
+    G = graph_n.numel()
+    nt = q5.shape[-1]
+    heat = torch.empty((G, nt), dtype=torch.float64, device=q5.device)
+    flags = torch.empty(G, dtype=torch.int32, device=q5.device)
+    _check(lib().slaq_closure_apply(_ptr(yhat), _ptr(q5), _ptr(qr), G, nv, nt, _ptr(graph_n), ctypes.c_double(tol),
+                                    _ptr(heat), _ptr(flags), _stream(stream)))
+    return heat, flags
 
 
 def profile_enable(on=True):

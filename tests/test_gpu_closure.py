@@ -1,0 +1,145 @@
+"""GPU tests of the learned closure: BF16-MFMA forward/backward against the
+FP64 reference, the per-probe Gauss / Radau rules against the oracle, training
+convergence, the gain over plain 5-step SLQ, and the forced fallback."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as OM
+from oracle import radau as OR
+from oracle import slq as O
+from paper_2003_01282_amd import closure as C
+from paper_2003_01282_amd import inputs
+from paper_2003_01282_amd import slaq as S
+
+pytestmark = pytest.mark.gpu
+
+T = O.t_grid(256)
+
+
+def bf16_round(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def oracle_layers(net):
+    # the kernels multiply with BF16 weights and FP32 biases
+    return [(bf16_round(W.cpu().numpy()), b.cpu().numpy().astype(np.float64)) for W, b in net.layers()]
+
+
+def test_forward_and_gradients_against_fp64_reference():
+    print("\n[gpu] closure gradient check", flush=True)
+    net = S.Closure(d_in=10, hidden=256, nt=256, seed=7)
+    rng = np.random.default_rng(0)
+    B = 300  # ragged against the 64-row tiles
+    X = np.zeros((B, 32), dtype=np.float32)
+    X[:, :5] = np.sort(rng.uniform(0, 2, (B, 5)), axis=1)
+    X[:, 5:10] = rng.dirichlet(np.ones(5), B)
+    Y = rng.standard_normal((B, 256)).astype(np.float32) * 0.1
+    x = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    y = torch.from_numpy(Y).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    net.train_step(x, y, 0.0, loss=loss)
+    grads = net.layers(net.get(1))
+    params = oracle_layers(net)
+    Xo = x.to(torch.float64).cpu().numpy()
+    yh, _ = OM.forward(params, Xo)
+    yg = net.forward(x).cpu().numpy()
+    assert np.linalg.norm(yg - yh) / np.linalg.norm(yh) < 1e-2
+    lo, go = OM.loss_and_grads(params, Xo, Y.astype(np.float64))
+    assert abs(float(loss.item()) - lo) / lo < 1e-2
+    for l in range(4):
+        for k in range(2):
+            g_gpu = grads[l][k].cpu().numpy().astype(np.float64).ravel()
+            g_ref = go[l][k].ravel()
+            if l == 0 and k == 0:  # padded input rows carry no gradient
+                g_gpu = g_gpu.reshape(32, -1)[:10].ravel()
+                g_ref = g_ref.reshape(32, -1)[:10].ravel()
+            rel = np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)
+            cos = g_gpu @ g_ref / (np.linalg.norm(g_gpu) * np.linalg.norm(g_ref))
+            print(f"layer {l} {'Wb'[k]}: rel {rel:.2e} cos {cos:.6f}")
+            assert rel < 1e-2 and cos > 0.999, (l, k, rel, cos)
+
+
+def test_probe_rules_against_oracle():
+    print("\n[gpu] closure rules", flush=True)
+    csr = inputs.chung_lu(1200, 5000, 2.5, seed=5)
+    nv, m = 16, 30
+    og = O.build_graph(csr.n, csr.row_ptr, csr.col_idx)
+    a, b, s = O.lanczos(og, nv, m, seed=4)
+    da, db, ds = (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), torch.from_numpy(s).cuda())
+    th5, w5, thr, wr = S.closure_rules(da, db, ds, mf=5)
+    tt = torch.from_numpy(T).cuda()
+    q5 = S.gauss_values(th5, w5, tt).cpu().numpy()
+    qr = S.gauss_values(thr, wr, tt).cpu().numpy()
+    lo, hi = OR.heat_bracket(a[:, :5], b[:, :5], np.minimum(s, 5), T)
+    np.testing.assert_allclose(q5, lo, rtol=1e-12)
+    np.testing.assert_allclose(qr, hi, rtol=1e-10)
+    th_o, w_o = O.ritz(a[:, :5], b[:, :5], np.minimum(s, 5))
+    X = S.closure_features(th5, w5).to(torch.float64).cpu().numpy()
+    np.testing.assert_allclose(X[:, :10], bf16_round(OM.features(th_o, w_o, np.minimum(s, 5))), rtol=0, atol=1e-12)
+    # the exact quadratic forms lie inside the GPU bracket
+    from oracle import exact
+    lam, Phi = np.linalg.eigh(exact.dense_laplacian(og))
+    mu2 = (Phi.T @ (O.rademacher(csr.n, nv, 4) / np.sqrt(csr.n))) ** 2
+    ex = np.einsum("ip,it->pt", mu2, np.exp(-lam[:, None] * T[None, :]))
+    assert np.all(q5 <= ex * (1 + 1e-12)) and np.all(ex <= qr * (1 + 1e-12))
+
+
+def closure_graphs(count, seed, n_lo=500, n_hi=3000):
+    return [inputs.closure_graph(i, seed=seed, n_lo=n_lo, n_hi=n_hi) for i in range(count)]
+
+
+@pytest.fixture(scope="module")
+def trained():
+    tt = torch.from_numpy(T).cuda()
+    train_g = closure_graphs(120, seed=1)
+    test_g = closure_graphs(30, seed=2)
+    dtr = C.probe_data(train_g, nv=20, t=tt, seed=100)
+    dte = C.probe_data(test_g, nv=20, t=tt, seed=900)
+    net = S.Closure(d_in=10, hidden=256, nt=256, seed=3)
+    hist = C.train(net, dtr, epochs=60, batch=256, lr=2e-3, seed=0)
+    return net, dtr, dte, hist, test_g
+
+
+def test_training_converges(trained):
+    net, dtr, dte, hist, _ = trained
+    print(f"\n[gpu] closure loss {hist[0]:.3e} -> {hist[-1]:.3e}", flush=True)
+    assert hist[-1] < 0.2 * hist[0]
+
+
+def test_closure_gain_over_plain_five_steps(trained):
+    net, dtr, dte, hist, test_g = trained
+    ref = C.heat_from_q(dte.q_hi, dte.graph_n, 20).cpu().numpy()      # plain m = 30, same probes
+    plain5 = C.heat_from_q(dte.q5, dte.graph_n, 20).cpu().numpy()     # plain m = 5
+    heat, flags = C.infer(net, dte, tol=1e-3)
+    e_plain = C.rel_l2(plain5, ref)
+    e_clo = C.rel_l2(heat.cpu().numpy(), ref)
+    print(f"\n[gpu] held-out rel-l2 vs m=30: plain m=5 median {np.median(e_plain):.2e} max {e_plain.max():.2e}; "
+          f"closure median {np.median(e_clo):.2e} max {e_clo.max():.2e}; flagged {int(flags.sum())}/{len(test_g)}",
+          flush=True)
+    assert np.median(e_clo) < np.median(e_plain)
+    # predictions are clamped to the Gauss / Radau bracket
+    q5 = C.heat_from_q(dte.q5, dte.graph_n, 20).cpu().numpy()
+    qr = C.heat_from_q(dte.qr, dte.graph_n, 20).cpu().numpy()
+    h = heat.cpu().numpy()
+    assert np.all(h >= q5 * (1 - 1e-12)) and np.all(h <= qr * (1 + 1e-12))
+
+
+def test_forced_fallback_reproduces_plain(trained):
+    net, dtr, dte, hist, test_g = trained
+    tt = torch.from_numpy(T).cuda()
+    # a negative tolerance rejects every prediction: every graph falls back
+    heat, flags = C.heat_with_fallback(net, dte, test_g, nv=20, t=tt, seed=900, tol=-1.0)
+    assert int(flags.sum()) == len(test_g)
+    for i in (0, 7, 19):
+        a, b, s = C.lanczos_graph(test_g[i], 20, 30, 900 + i)
+        th, w2 = S.ritz(a, b, s)
+        plain = S.signature(th, w2, test_g[i].n, tt).cpu().numpy()
+        assert np.array_equal(heat[i], plain)
+    # with the normal tolerance only flagged graphs are recomputed
+    heat2, flags2 = C.heat_with_fallback(net, dte, test_g, nv=20, t=tt, seed=900, tol=1e-3)
+    h_clo, _ = C.infer(net, dte, tol=1e-3)
+    h_clo = h_clo.cpu().numpy()
+    for i in range(len(test_g)):
+        if not flags2[i]:
+            assert np.array_equal(heat2[i], h_clo[i])
