@@ -225,9 +225,10 @@ slaq_status slaq_batch_destroy(slaq_batch_t b);
  * gauss_values: Q[count][nt] from the first kn of ks nodes per probe.
  * targets: y = log(q_hi) - log(q_lo) elementwise (FP32).
  * apply: per probe Q_hat = q5 exp(y_hat) clamped to [q5, qr]; heat[g][t] =
- * graph_n[g]/nv sum over the graph's nv probes; flags[g] = 1 when a raw
- * prediction left the bracket by more than tol (relative) - such graphs are
- * to be recomputed by plain SLQ. */
+ * graph_n[g]/nv sum over the graph's nv probes; flags[g] = 1 when at some t
+ * the graph's bracket is wider than tol (relative) and clamping moved the
+ * graph's heat by more than tol - such graphs are to be recomputed by plain
+ * SLQ (tol < 0 flags every graph). */
 typedef struct slaq_closure_s* slaq_closure_t;
 slaq_status slaq_closure_create(int d_in, int hidden, int nt, uint64_t seed, void* stream, slaq_closure_t* out);
 slaq_status slaq_closure_destroy(slaq_closure_t c);

@@ -340,9 +340,13 @@ __global__ void __launch_bounds__(256) log_ratio(int64_t total, const double* __
     if (i < total) y[i] = (float)(log(Qa[i]) - log(Qb[i]));
 }
 
-// Q_hat = Q5 exp(y_hat) clamped to [Q5, QR]; flags[g] |= 1 when the raw
-// prediction leaves the bracket by more than tol relative.  One block per
-// graph, threads over t; heat[g][b] = n_g / nv sum_p Q_hat.
+// Q_hat = Q5 exp(y_hat) clamped to [Q5, QR] per probe; heat[g][b] =
+// n_g / nv sum_p Q_hat.  Where the graph's bracket is narrower than tol
+// (relative) the clamped value is within tol of every value the bracket
+// allows, whatever the network said.  flags[g] = 1 when, at some time, the
+// bracket is wider than tol AND clamping moved the graph's heat by more than
+// tol: there the prediction disagrees with a bound that cannot vouch for it.
+// One block per graph.
 __global__ void __launch_bounds__(256) closure_apply(int G, int nv, int nt, const float* __restrict__ yhat,
                                                      const double* __restrict__ Q5, const double* __restrict__ QR,
                                                      const int64_t* __restrict__ gn, double tol,
@@ -350,14 +354,17 @@ __global__ void __launch_bounds__(256) closure_apply(int G, int nv, int nt, cons
     const int g = blockIdx.x;
     int bad = 0;
     for (int b = threadIdx.x; b < nt; b += blockDim.x) {
-        double s = 0.0;
+        double s = 0.0, raw = 0.0, slo = 0.0, shi = 0.0;
         for (int p = 0; p < nv; ++p) {
             const int64_t o = ((int64_t)g * nv + p) * nt + b;
             const double lo = Q5[o], hi = QR[o];
             const double q = lo * exp((double)yhat[o]);
-            if (q < lo * (1.0 - tol) || q > hi * (1.0 + tol) || !(q == q)) bad = 1;
+            raw += q;
+            slo += lo;
+            shi += hi;
             s += q < lo ? lo : (q > hi ? hi : q);
         }
+        if (!(shi - slo <= tol * s) && !(fabs(raw - s) <= tol * s)) bad = 1;
         heat[(int64_t)g * nt + b] = (double)gn[g] / nv * s;
     }
     __shared__ int any;

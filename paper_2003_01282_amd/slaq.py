@@ -202,7 +202,7 @@ def lanczos(g, nv, m, seed, workspace=None, out=None, stream=None):
                torch.empty((nv, m), dtype=torch.float64, device=dev),
                torch.empty(nv, dtype=torch.int32, device=dev))
     alpha, beta, steps = out
-    _check(lib().slaq_lanczos(g.handle, nv, m, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(alpha), _ptr(beta),
+    _check(lib().slaq_lanczos(g.handle, nv, m, ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(alpha), _ptr(beta),
                               _ptr(steps), _ptr(workspace), workspace.numel(), _stream(stream)))
     return alpha, beta, steps
 
@@ -308,7 +308,7 @@ def batch_run(b, seed, t=None, heat=True, vnge=True, ritz=False, coeffs=False, g
         o["tau2"] = torch.empty((b.G, b.nv, b.m), dtype=f64, device=dev)
         o.setdefault("steps", torch.empty((b.G, b.nv), dtype=torch.int32, device=dev))
     g = o.get
-    _check(lib().slaq_batch_run(b.handle, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(t), _ptr(g("heat")),
+    _check(lib().slaq_batch_run(b.handle, ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(t), _ptr(g("heat")),
                                 _ptr(g("vnge")), _ptr(g("alpha")), _ptr(g("beta")), _ptr(g("steps")),
                                 _ptr(g("theta")), _ptr(g("tau2")), SLAQ_BATCH_GRAPH if graph else 0,
                                 _stream(stream)))
