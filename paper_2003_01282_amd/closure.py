@@ -27,17 +27,22 @@ class ProbeData:
     nv: int
 
 
+def graph_nodes(csr):
+    return csr.n if hasattr(csr, "n") else csr[0].numel() - 1
+
+
 def lanczos_graph(csr, nv, m, seed):
-    rp, ci = S.to_device(csr)
+    rp, ci = S.to_device(csr) if hasattr(csr, "row_ptr") else csr
     g = S.build_graph(rp, ci)
     return S.lanczos(g, nv, m, seed)
 
 
 def probe_data(graphs, nv, t, m_hi=30, mf=5, seed=0, labels=True):
     """Runs the plain path per graph (graph i uses seed + i) and assembles the
-    closure's inputs (and labels when requested).  With labels=False only
-    mf + 1 steps are run (beta_mf is needed for the Radau bracket)."""
-    m = m_hi if labels else mf + 1
+    closure's inputs (and labels when requested).  With labels=False only mf
+    steps are run (step mf also yields beta_mf, the Radau bracket's coupling).
+    `graphs` holds host CSRs or (row_ptr, col_idx) device tensor pairs."""
+    m = m_hi if labels else mf
     A, B, St = [], [], []
     for i, csr in enumerate(graphs):
         a, b, s = lanczos_graph(csr, nv, m, seed + i)
@@ -56,7 +61,7 @@ def probe_data(graphs, nv, t, m_hi=30, mf=5, seed=0, labels=True):
         th, w2 = S.ritz(alpha, beta, steps)
         q_hi = S.gauss_values(th, w2, t)
         y = S.closure_targets(q_hi, q5)
-    gn = torch.tensor([c.n for c in graphs], dtype=torch.int64, device="cuda")
+    gn = torch.tensor([graph_nodes(c) for c in graphs], dtype=torch.int64, device="cuda")
     return ProbeData(x=x, q5=q5, qr=qr, q_hi=q_hi, y=y, graph_n=gn, nv=nv)
 
 
@@ -102,7 +107,7 @@ def heat_with_fallback(net, data, graphs, nv, t, seed=0, tol=1e-3, m_plain=30):
     for i in np.flatnonzero(flags):
         a, b, s = lanczos_graph(graphs[i], nv, m_plain, seed + i)
         th, w2 = S.ritz(a, b, s)
-        heat[i] = S.signature(th, w2, graphs[i].n, t).cpu().numpy()
+        heat[i] = S.signature(th, w2, graph_nodes(graphs[i]), t).cpu().numpy()
     return heat, flags
 
 

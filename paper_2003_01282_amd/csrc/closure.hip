@@ -684,8 +684,8 @@ slaq_status slaq_closure_rules(const double* alpha, const double* beta, const in
                                int mf, double* theta, double* tau2, double* theta_r, double* tau2_r, void* stream) {
     clear_error();
     SLAQ_REQUIRE(alpha && beta && steps && theta && tau2 && theta_r && tau2_r, SLAQ_ERR_INVALID_ARG, "NULL pointer");
-    SLAQ_REQUIRE(count >= 1 && mf >= 1 && mf < ms && ms <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG,
-                 "need count >= 1 and 1 <= mf < ms <= %d (beta_mf must exist)", SLAQ_MAX_STEPS);
+    SLAQ_REQUIRE(count >= 1 && mf >= 1 && mf <= ms && ms <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG,
+                 "need count >= 1 and 1 <= mf <= ms <= %d", SLAQ_MAX_STEPS);
     hipLaunchKernelGGL(probe_rules, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, (hipStream_t)stream, count,
                        alpha, beta, steps, ms, mf, theta, tau2, theta_r, tau2_r);
     SLAQ_LAUNCHED();

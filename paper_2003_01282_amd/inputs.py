@@ -207,3 +207,75 @@ def closure_graph(idx, seed=0, n_lo=1_000, n_hi=100_000, mean_degree=10.0):
         p_out = mean_degree / (15.0 * n / k + (n - n / k))
         return sbm(n, k, min(15.0 * p_out, 1.0), p_out, seed=gs)
     return erdos_renyi(n, mean_degree / (n - 1), seed=gs)
+
+
+# ---------------------------------------------------------------------------
+# Device generators for large graph populations (same families and
+# parameters as closure_graph, drawn with torch's device RNG; the graphs are
+# not the same draws as the numpy generators').  Return (row_ptr int64,
+# col_idx int32) device tensors.
+# ---------------------------------------------------------------------------
+def _csr_from_pairs_torch(n, u, v):
+    import torch
+    keep = u != v
+    u, v = u[keep], v[keep]
+    lo = torch.minimum(u, v)
+    hi = torch.maximum(u, v)
+    key = torch.unique(lo * n + hi)
+    lo = key // n
+    hi = key - lo * n
+    both, _ = torch.sort(torch.cat([lo * n + hi, hi * n + lo]))
+    rows = both // n
+    cols = (both - rows * n).to(torch.int32)
+    counts = torch.bincount(rows, minlength=n)
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=u.device)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return row_ptr, cols
+
+
+def closure_graph_device(idx, seed=0, n_lo=1_000, n_hi=100_000, mean_degree=10.0, device="cuda"):
+    """Device counterpart of closure_graph: n log-uniform on [n_lo, n_hi],
+    family idx mod 3 (Chung-Lu gamma 2.5 / 2-5 block SBM with p_in = 15 p_out /
+    Erdos-Renyi), expected mean degree `mean_degree`."""
+    import torch
+    rng = _rng(seed, 7, idx)
+    n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(0, 2**62)))
+    fam = idx % 3
+    if fam == 0:
+        w = (torch.arange(n, dtype=torch.float64, device=device) + 1.0) ** (-1.0 / 1.5)
+        cdf = torch.cumsum(w, 0)
+        cdf /= cdf[-1].clone()
+        m = int(mean_degree * n / 2)
+        u = torch.searchsorted(cdf, torch.rand(m, dtype=torch.float64, device=device, generator=gen), right=True)
+        v = torch.searchsorted(cdf, torch.rand(m, dtype=torch.float64, device=device, generator=gen), right=True)
+        return _csr_from_pairs_torch(n, u.clamp_(max=n - 1), v.clamp_(max=n - 1))
+    if fam == 2:
+        m = int(rng.binomial(n * (n - 1) // 2, mean_degree / (n - 1)))
+        u = torch.randint(0, n, (m,), device=device, generator=gen)
+        v = torch.randint(0, n, (m,), device=device, generator=gen)
+        return _csr_from_pairs_torch(n, u, v)
+    k = int(rng.integers(2, 6))
+    p_out = mean_degree / (15.0 * n / k + (n - n / k))
+    p_in = min(15.0 * p_out, 1.0)
+    lab = torch.randint(0, k, (n,), device=device, generator=gen)
+    order = torch.argsort(lab)
+    sizes = torch.bincount(lab, minlength=k).cpu().numpy()
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    us, vs = [], []
+    for x in range(k):
+        for y in range(x, k):
+            nx, ny = int(sizes[x]), int(sizes[y])
+            if nx == 0 or ny == 0:
+                continue
+            pairs = nx * (nx - 1) // 2 if x == y else nx * ny
+            cnt = int(rng.binomial(pairs, p_in if x == y else p_out))
+            iu = torch.randint(0, nx, (cnt,), device=device, generator=gen) + int(starts[x])
+            iv = torch.randint(0, ny, (cnt,), device=device, generator=gen) + int(starts[y])
+            us.append(order[iu])
+            vs.append(order[iv])
+    if not us:
+        e = torch.zeros(0, dtype=torch.int64, device=device)
+        return _csr_from_pairs_torch(n, e, e)
+    return _csr_from_pairs_torch(n, torch.cat(us), torch.cat(vs))
