@@ -184,8 +184,11 @@ def bench_closure(args):
     train_g = gen(ntr, spec["seed"])
     test_g = gen(nte, spec["seed"] + 1)
     log(f"graphs ready in {time.perf_counter() - t0:.1f} s")
+    # the last tenth of the training population is held back to tune the gate
+    nval = max(ntr // 10, 1)
+    fit_g, val_g = train_g[:-nval], train_g[-nval:]
     t0 = time.perf_counter()
-    dtr = C.probe_data(train_g, nv=nv, t=t, seed=100)
+    dtr = C.probe_data(fit_g, nv=nv, t=t, seed=100)
     log(f"training data ({dtr.x.shape[0]} probes) in {time.perf_counter() - t0:.1f} s")
     dte = C.probe_data(test_g, nv=nv, t=t, seed=7_000_000)
     net = S.Closure(d_in=2 * mf, hidden=256, nt=256, seed=3)
@@ -208,6 +211,10 @@ def bench_closure(args):
     mfma_s = (fwd[1] + bwd[1]) * 1e-3
     tflops = 3 * fl_fwd * samples / mfma_s / 1e12 if mfma_s > 0 else None
 
+    # gate tolerance retuned on the validation graphs (labels: plain m = 30)
+    dval = C.probe_data(val_g, nv=nv, t=t, seed=100 + len(fit_g))
+    gate_tol, gate_table = C.tune_gate(net, dval, nv)
+    log(f"gate tolerance {gate_tol}: {gate_table}")
     ref = C.heat_from_q(dte.q_hi, dte.graph_n, nv).cpu().numpy()
     rows = {}
 
@@ -233,7 +240,7 @@ def bench_closure(args):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dinf = C.probe_data(test_g, nv=nv, t=t, seed=7_000_000, labels=False, mf=mf)
-    heat, flags = C.heat_with_fallback(net, dinf, test_g, nv=nv, t=t, seed=7_000_000, tol=1e-3)
+    heat, flags = C.heat_with_fallback(net, dinf, test_g, nv=nv, t=t, seed=7_000_000, tol=gate_tol)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     e = C.rel_l2(heat, ref)
@@ -260,6 +267,7 @@ def bench_closure(args):
                    "m_closure": mf, "m_label": 30, "nt": 256, "n_range": [spec["n_lo"], spec["n_hi"]],
                    "epochs": args.closure_epochs},
         "methods": rows,
+        "gate": {"tolerance": gate_tol, "validation": gate_table},
         "cheapest_plain_at_least_as_accurate": best_plain,
         "speedup_vs_that_plain": rows["closure_m5"]["graphs_per_s"] / rows[best_plain]["graphs_per_s"],
         "training": {"loss_first": hist[0], "loss_last": hist[-1], "seconds": train_s, "samples": samples,

@@ -139,7 +139,8 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
 /* Gauss nodes and weights (§3.1, eq. "quadratic"): theta[p*m+k] are the
  * eigenvalues of T_p (size steps[p]) and tau2[p*m+k] the squared first
  * components of its normalized eigenvectors; entries k >= steps[p] are 0.
- * FP64 implicit-shift QL per probe. */
+ * FP64 implicit-shift QR per probe; nv may be any count of independent
+ * probes (nv * m < 2^31), e.g. the probes of many graphs at once. */
 slaq_status slaq_ritz(const double* alpha, const double* beta, const int32_t* steps,
                       int nv, int m, double* theta, double* tau2, void* stream);
 

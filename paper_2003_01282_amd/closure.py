@@ -111,6 +111,26 @@ def heat_with_fallback(net, data, graphs, nv, t, seed=0, tol=1e-3, m_plain=30):
     return heat, flags
 
 
+def tune_gate(net, dval, nv, candidates=(1e-3, 2e-3, 5e-3, 1e-2, 2e-2, 5e-2, 1e-1, 1.0),
+              target=1e-3, min_ok=0.99):
+    """Largest gate tolerance whose outcome on validation graphs keeps at
+    least `min_ok` of them within `target` (relative l2 against the labels,
+    plain m_hi SLQ on the same probes; flagged graphs count as exact since
+    they fall back to it).  Returns (tolerance, table)."""
+    ref = heat_from_q(dval.q_hi, dval.graph_n, nv).cpu().numpy()
+    table = []
+    best = None
+    for tol in sorted(candidates):
+        heat, flags = infer(net, dval, tol)
+        e = rel_l2(heat.cpu().numpy(), ref)
+        f = flags.cpu().numpy().astype(bool)
+        ok = float(np.mean(np.where(f, True, e <= target)))
+        table.append({"tol": tol, "fallback": float(f.mean()), "ok": ok})
+        if ok >= min_ok:
+            best = tol
+    return (best if best is not None else min(candidates)), table
+
+
 def rel_l2(a, b):
     a = np.asarray(a)
     b = np.asarray(b)

@@ -93,8 +93,7 @@ slaq_status slaq_ritz(const double* alpha, const double* beta, const int32_t* st
                       double* theta, double* tau2, void* stream) {
     clear_error();
     SLAQ_REQUIRE(alpha && beta && steps && theta && tau2, SLAQ_ERR_INVALID_ARG, "NULL pointer argument");
-    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
-                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(nv >= 1 && (int64_t)nv * m <= INT32_MAX, SLAQ_ERR_INVALID_ARG, "need nv >= 1 and nv * m < 2^31");
     SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
     const int B = m <= 32 ? 64 : 32;  // keeps the LDS tile at <= 48 KB
     const size_t lds = (size_t)3 * B * m * sizeof(double);
@@ -108,8 +107,7 @@ slaq_status slaq_signature(const double* theta, const double* tau2, int nv, int 
                            const double* t, int nt, int kind, double* out, void* stream) {
     clear_error();
     SLAQ_REQUIRE(theta && tau2 && t && out, SLAQ_ERR_INVALID_ARG, "NULL pointer argument");
-    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
-                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(nv >= 1 && (int64_t)nv * m <= INT32_MAX, SLAQ_ERR_INVALID_ARG, "need nv >= 1 and nv * m < 2^31");
     SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
     SLAQ_REQUIRE(n > 0, SLAQ_ERR_INVALID_ARG, "n must be positive");
     SLAQ_REQUIRE(nt >= 1 && nt <= 65535, SLAQ_ERR_INVALID_ARG, "nt must be in [1, 65535]");

@@ -226,7 +226,7 @@ def test_argument_errors_before_launch():
     csr = inputs.cycle(10)
     rp, ci = S.to_device(csr)
     g = S.build_graph(rp, ci)
-    for nv, m in ((0, 5), (5000, 5), (4, 0), (4, 65)):
+    for nv, m in ((0, 5), (5000, 5), (4, 0), (4, 65)):  # lanczos: nv <= 4096, m <= 64
         with pytest.raises(S.SlaqError) as e:
             S.lanczos(g, nv, m, 1, workspace=torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
         assert e.value.status == 1
