@@ -97,15 +97,25 @@ slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* tr
                             int64_t* n_isolated, double* max_degree);
 
 /* Row schedule of the SpMM.  Rows with at least heavy_min nonzeros are cut
- * into pieces of at most `piece` nonzeros that separate waves reduce in
- * parallel (defaults 256 and 512; heavy_min >= 32, piece a multiple of 64 and
- * >= 64).  Setting it rebuilds the piece plan on `stream`; query
+ * at the 8 column-id boundaries of equal nnz mass (the first id whose row
+ * offset reaches nnz/8 * x) and each part into pieces of at most `piece`
+ * nonzeros that separate waves reduce in parallel; the pieces of column range
+ * x run on workgroups b with b % 8 == x, i.e. one XCD, so that XCD's L2 holds
+ * only that range's rows (defaults 256 and 512; heavy_min >= 128, piece a
+ * multiple of 64 and >= 64).  Setting it rebuilds the piece plan on `stream`; query
  * slaq_lanczos_workspace again afterwards, its size depends on the schedule.
  * slaq_graph_schedule reports the schedule and (waiting for the stream of the
  * build) the number of heavy rows and pieces; any pointer may be NULL. */
 slaq_status slaq_graph_set_schedule(slaq_graph_t g, int heavy_min, int piece, void* stream);
 slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int64_t* n_heavy,
                                 int64_t* n_pieces);
+
+/* Probe tile of the gather kernels, in float4 words (4 probes): the SpMM
+ * runs once per tile of the probe block, tiles one after another, so the
+ * gathered rows of a tile stay in cache longer, at the price of visiting
+ * every nonzero once per tile.  0 (default) = tiles of 64 words (256 probes).
+ * Changes the workspace size. */
+slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads);
 
 /* Frees the host handle (never caller memory). */
 slaq_status slaq_graph_destroy(slaq_graph_t g);

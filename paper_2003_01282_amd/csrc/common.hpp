@@ -66,8 +66,12 @@ struct BuildPartial {
 // are tunable (slaq_graph_set_schedule); these are the defaults and bounds.
 constexpr int kDefaultHeavyMin = 256;
 constexpr int kDefaultPiece = 512;
-constexpr int kMinHeavyMin = 32;
+constexpr int kMinHeavyMin = 128;
 constexpr int kMinPiece = 64;
+// Heavy rows are also cut at kColRanges column-id boundaries of equal nnz
+// mass; the pieces of range x are reduced by workgroups b with b % 8 == x,
+// i.e. on one XCD, whose L2 then holds only that range's hot rows.
+constexpr int kColRanges = 8;
 
 }  // namespace slaq
 
@@ -83,10 +87,16 @@ struct slaq_graph_s {
     slaq::BuildPartial* partials;
     long long* blockcounts;  // [nplan] heavy rows, pieces per plan block, then offsets
     int32_t* hrow;           // heavy row ids, increasing
-    int64_t* hoff;           // first piece of each heavy row, hoff[n_heavy] = n_pieces
-    int64_t max_heavy;       // capacity of hrow / hoff
+    int64_t* hoff;           // (row-major piece offsets; kept for the counts)
+    int64_t* bounds;         // [kColRanges + 1] column-id boundaries of equal nnz mass
+    int64_t* segk;           // [(kColRanges + 1) * max_heavy]: first nonzero of range x in heavy row h
+    int64_t* segoff;         // [kColRanges * max_heavy + 1]: first piece of (x, h), x-major
+    long long* segcnt;       // [kColRanges * max_heavy] pieces of (x, h) before the scan
+    long long* scanbuf;      // block sums of the segment scan
+    int64_t max_heavy;       // capacity of hrow / hoff / segk (stride of the x-major arrays)
     int heavy_min;
     int piece;
+    int tile_quads;          // probe tile of the gather kernels in float4 words (0 = automatic)
     hipStream_t stream;      // stream of the build (slaq_graph_info waits on it)
 };
 

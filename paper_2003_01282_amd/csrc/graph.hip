@@ -273,9 +273,115 @@ __global__ void __launch_bounds__(kPlanBlock) plan_write(int64_t n, const int64_
     }
 }
 
+// ---- column-range segments of heavy rows (x-major layout, stride cap) ----
+__global__ void __launch_bounds__(64) xcd_bounds(int64_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                                                 int64_t* __restrict__ bounds) {
+    const int x = threadIdx.x;
+    if (x > kColRanges) return;
+    const int64_t target = nnz / kColRanges * x;
+    int64_t lo = 0, hi = n;  // smallest i with rp[i] >= target
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (rp[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    bounds[x] = x == 0 ? 0 : (x == kColRanges ? n : lo);
+}
+
+__global__ void __launch_bounds__(256) seg_count(int64_t cap, const GraphStats* __restrict__ st,
+                                                 const int32_t* __restrict__ hrow, const int64_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col, const int64_t* __restrict__ bounds,
+                                                 int piece, int64_t* __restrict__ segk, long long* __restrict__ cnt) {
+    const int64_t h = blockIdx.x * 256LL + threadIdx.x;
+    if (h >= cap) return;
+    const int64_t nh = st->n_heavy;
+    if (h >= nh) {
+        for (int x = 0; x < kColRanges; ++x) cnt[x * cap + h] = 0;
+        return;
+    }
+    const int64_t row = hrow[h], s = rp[row], e = rp[row + 1];
+    int64_t prev = s;
+    segk[h] = s;
+    for (int x = 1; x <= kColRanges; ++x) {
+        int64_t k = e;
+        if (x < kColRanges) {
+            const int64_t b = bounds[x];
+            int64_t lo = prev, hi = e;  // first nonzero with column >= b
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if ((int64_t)col[mid] < b) lo = mid + 1; else hi = mid;
+            }
+            k = lo;
+        }
+        segk[x * cap + h] = k;
+        cnt[(x - 1) * cap + h] = (k - prev + piece - 1) / piece;
+        prev = k;
+    }
+}
+
+// exclusive scan of cnt[0..len) in place, len = kColRanges * cap, blocks of 1024
+__global__ void __launch_bounds__(1024) seg_scan_blocks(int64_t len, const long long* __restrict__ cnt,
+                                                        long long* __restrict__ bsum) {
+    __shared__ long long red[1024];
+    const int64_t i = blockIdx.x * 1024LL + threadIdx.x;
+    red[threadIdx.x] = i < len ? cnt[i] : 0;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(1024) seg_scan_top(int64_t nb, long long* __restrict__ bsum,
+                                                     GraphStats* __restrict__ st, int64_t* __restrict__ total_out) {
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = b0 + per < nb ? b0 + per : nb;
+    long long s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += bsum[b];
+    __shared__ long long sh[1024];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        long long a = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    long long run = t > 0 ? sh[t - 1] : 0;
+    for (int64_t b = b0; b < b1; ++b) {
+        const long long v = bsum[b];
+        bsum[b] = run;
+        run += v;
+    }
+    if (t == 1023) {
+        st->n_pieces = sh[1023];
+        *total_out = sh[1023];
+    }
+}
+
+__global__ void __launch_bounds__(1024) seg_scan_apply(int64_t len, const long long* __restrict__ cnt,
+                                                       const long long* __restrict__ boff,
+                                                       int64_t* __restrict__ segoff) {
+    __shared__ long long sh[1024];
+    const int t = threadIdx.x;
+    const int64_t i = blockIdx.x * 1024LL + t;
+    const long long v = i < len ? cnt[i] : 0;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        long long a = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    if (i < len) segoff[i] = boff[blockIdx.x] + sh[t] - v;
+}
+
 struct ScratchLayout {
-    size_t off_stats, off_part, off_counts, off_hrow, off_hoff, total;
-    int64_t nplan, max_heavy;
+    size_t off_stats, off_part, off_counts, off_hrow, off_hoff, off_bounds, off_segk, off_cnt, off_segoff, off_bsum,
+        total;
+    int64_t nplan, max_heavy, seg_blocks;
 };
 
 static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
@@ -294,6 +400,18 @@ static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     off += align_up(sizeof(int32_t) * (size_t)(L.max_heavy + 1), 256);
     L.off_hoff = off;
     off += align_up(sizeof(int64_t) * (size_t)(L.max_heavy + 1), 256);
+    const size_t cap = (size_t)(L.max_heavy > 0 ? L.max_heavy : 1);
+    L.off_bounds = off;
+    off += align_up(sizeof(int64_t) * (kColRanges + 1), 256);
+    L.off_segk = off;
+    off += align_up(sizeof(int64_t) * (kColRanges + 1) * cap, 256);
+    L.off_cnt = off;
+    off += align_up(sizeof(long long) * kColRanges * cap, 256);
+    L.off_segoff = off;
+    off += align_up(sizeof(int64_t) * (kColRanges * cap + 1), 256);
+    L.seg_blocks = (int64_t)((kColRanges * cap + 1023) / 1024);
+    L.off_bsum = off;
+    off += align_up(sizeof(long long) * (size_t)L.seg_blocks, 256);
     L.total = off;
     return L;
 }
@@ -309,6 +427,21 @@ slaq_status build_plan(slaq_graph_s* g, hipStream_t st) {
     SLAQ_LAUNCHED();
     hipLaunchKernelGGL(plan_write, dim3((unsigned)nplan), dim3(kPlanBlock), 0, st, g->n, g->row_ptr,
                        g->heavy_min, g->piece, offs, g->hrow, g->hoff);
+    SLAQ_LAUNCHED();
+    // column-range segments and their pieces
+    const int64_t cap = g->max_heavy > 0 ? g->max_heavy : 1;
+    const int64_t len = kColRanges * cap;
+    const int64_t nb = (len + 1023) / 1024;
+    hipLaunchKernelGGL(xcd_bounds, dim3(1), dim3(64), 0, st, g->n, g->nnz, g->row_ptr, g->bounds);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(seg_count, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, cap, g->stats, g->hrow,
+                       g->row_ptr, g->col_idx, g->bounds, g->piece, g->segk, g->segcnt);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(seg_scan_blocks, dim3((unsigned)nb), dim3(1024), 0, st, len, g->segcnt, g->scanbuf);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(seg_scan_top, dim3(1), dim3(1024), 0, st, nb, g->scanbuf, g->stats, g->segoff + len);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(seg_scan_apply, dim3((unsigned)nb), dim3(1024), 0, st, len, g->segcnt, g->scanbuf, g->segoff);
     SLAQ_LAUNCHED();
     return SLAQ_OK;
 }
@@ -390,9 +523,15 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->blockcounts = (long long*)(base + SL.off_counts);
     g->hrow = (int32_t*)(base + SL.off_hrow);
     g->hoff = (int64_t*)(base + SL.off_hoff);
+    g->bounds = (int64_t*)(base + SL.off_bounds);
+    g->segk = (int64_t*)(base + SL.off_segk);
+    g->segcnt = (long long*)(base + SL.off_cnt);
+    g->segoff = (int64_t*)(base + SL.off_segoff);
+    g->scanbuf = (long long*)(base + SL.off_bsum);
     g->max_heavy = SL.max_heavy;
     g->heavy_min = kDefaultHeavyMin;
     g->piece = kDefaultPiece;
+    g->tile_quads = 0;
     g->row_ptr = row_ptr;
     g->n = n;
     g->nnz = nnz;
@@ -437,6 +576,14 @@ slaq_status slaq_graph_set_schedule(slaq_graph_t g, int heavy_min, int piece, vo
     g->heavy_min = heavy_min;
     g->piece = piece;
     return build_plan(g, (hipStream_t)stream);
+}
+
+slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    SLAQ_REQUIRE(tile_quads >= 0 && tile_quads <= 64, SLAQ_ERR_INVALID_ARG, "tile_quads must be in [0, 64]");
+    g->tile_quads = tile_quads;
+    return SLAQ_OK;
 }
 
 slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int64_t* n_heavy,

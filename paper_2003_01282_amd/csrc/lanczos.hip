@@ -27,6 +27,7 @@
 namespace slaq {
 
 constexpr double kEpsBreakdown = 1e-6;
+constexpr int kPieceUnroll = 8;  // gathers in flight per group in the piece kernel
 
 // Per-probe FP64 recurrence state (workspace).
 struct ProbeState {
@@ -71,7 +72,7 @@ __device__ __forceinline__ float4 load4(const float* p, int q) {
 // groups of each wave and the 4 waves of the block; writes one partial per
 // probe of this block's tile: part[p * nb + block].
 __device__ __forceinline__ void block_reduce_store(const double (&s)[4], double* __restrict__ part, int nb,
-                                                   int F, int G, int K, int ld) {
+                                                   int F, int G, int K, int ld, int tile, int TQ, int col0 = 0) {
     __shared__ double red[4][64][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -80,12 +81,12 @@ __device__ __forceinline__ void block_reduce_store(const double (&s)[4], double*
     const int t = threadIdx.x;
     if (t < 4 * G) {
         const int q = t >> 2, comp = t & 3;
-        const int p = blockIdx.y * (4 * kQuadsPerTile) + t;
-        if (blockIdx.y * kQuadsPerTile + q < F && p < ld) {
+        const int p = tile * (4 * TQ) + t;
+        if (tile * TQ + q < F && p < ld) {
             double a = 0.0;
             for (int wv = 0; wv < 4; ++wv)
                 for (int g = 0; g < K; ++g) a += red[wv][g * G + q][comp];
-            part[(int64_t)p * nb + blockIdx.x] = a;
+            part[(int64_t)p * nb + col0 + blockIdx.x] = a;
         }
     }
 }
@@ -183,16 +184,6 @@ __device__ __forceinline__ void group_segment(float4& acc, int64_t k0, int64_t k
     }
 }
 
-// largest h with hoff[h] <= p (hoff increasing, hoff[nh] > p)
-__device__ __forceinline__ int64_t piece_owner(const int64_t* __restrict__ hoff, int64_t nh, int64_t p) {
-    int64_t lo = 0, hi = nh - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (hoff[mid] <= p) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // index of row i in the increasing list hrow[0..nh)
 __device__ __forceinline__ int64_t heavy_index(const int32_t* __restrict__ hrow, int64_t nh, int64_t i) {
     int64_t lo = 0, hi = nh;
@@ -204,28 +195,52 @@ __device__ __forceinline__ int64_t heavy_index(const int32_t* __restrict__ hrow,
 }
 
 // One wave per piece: P[p] = sum over the piece's nonzeros of scale * R_j[col].
+// Pieces of column range x (x-major list) are taken by workgroups with
+// blockIdx.x % 8 == x, which the dispatcher places on one XCD; each wave walks
+// a contiguous run of its range's pieces so the owning heavy row advances
+// incrementally.
 template <int MODE, bool WEIGHTED>
 __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict__ st,
-                                                   const int32_t* __restrict__ hrow,
-                                                   const int64_t* __restrict__ hoff,
-                                                   const int64_t* __restrict__ rp,
+                                                   const int64_t* __restrict__ segk,
+                                                   const int64_t* __restrict__ segoff, int64_t cap,
                                                    const int32_t* __restrict__ col,
                                                    const float* __restrict__ w,
                                                    const float* __restrict__ diag,
                                                    const float4* __restrict__ R,
-                                                   float4* __restrict__ P, int F, int G, int K, int piece) {
+                                                   float4* __restrict__ P, int F, int G, int K, int piece,
+                                                   int tile0, int TQ) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
-    const int quad = blockIdx.y * kQuadsPerTile + gl;
+    const int tile = tile0 + (int)blockIdx.y;
+    const int quad = tile * TQ + gl;
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
-    const int64_t np = st->n_pieces, nh = st->n_heavy;
-    for (int64_t p = (int64_t)blockIdx.x * 4 + wave; p < np; p += (int64_t)gridDim.x * 4) {
-        const int64_t h = piece_owner(hoff, nh, p);
-        const int64_t row = hrow[h];
-        const int64_t e = rp[row + 1];
-        const int64_t k0 = rp[row] + (p - hoff[h]) * piece;
-        const int64_t k1 = k0 + piece < e ? k0 + piece : e;
+    const int64_t nh = st->n_heavy;
+    if (nh == 0) return;
+    const int x = blockIdx.x % kColRanges;
+    const int64_t waves_x = (int64_t)(gridDim.x / kColRanges) * 4;
+    const int64_t wi = (int64_t)(blockIdx.x / kColRanges) * 4 + wave;
+    const int64_t* so = segoff + (int64_t)x * cap;
+    const int64_t p_lo = so[0], p_hi = so[cap];
+    const int64_t per = (p_hi - p_lo + waves_x - 1) / waves_x;
+    const int64_t pa = p_lo + wi * per;
+    const int64_t pb = pa + per < p_hi ? pa + per : p_hi;
+    if (pa >= pb) return;
+    int64_t h;
+    {  // largest h < nh with so[h] <= pa
+        int64_t lo = 0, hi = nh - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (so[mid] <= pa) lo = mid; else hi = mid - 1;
+        }
+        h = lo;
+    }
+    for (int64_t p = pa; p < pb; ++p) {
+        while (so[h + 1] <= p) ++h;
+        const int64_t kstart = segk[(int64_t)x * cap + h];
+        const int64_t kend = segk[(int64_t)(x + 1) * cap + h];
+        const int64_t k0 = kstart + (p - so[h]) * piece;
+        const int64_t k1 = k0 + piece < kend ? k0 + piece : kend;
         float4 acc = f4(0.0f);
         // the wave loads 64 column indices at a time; group gi takes u = gi, gi+K, ...
         for (int64_t kb = k0; kb < k1; kb += 64) {
@@ -240,12 +255,12 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
             }
             const int rounds = (cnt + K - 1) / K;
             int r = 0;
-            for (; r + 4 <= rounds; r += 4) {
-                int32_t c[4];
-                float s[4];
-                float4 x[4];
+            for (; r + kPieceUnroll <= rounds; r += kPieceUnroll) {
+                int32_t c[kPieceUnroll];
+                float s[kPieceUnroll];
+                float4 x[kPieceUnroll];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
+                for (int v = 0; v < kPieceUnroll; ++v) {
                     const int u = (r + v) * K + gi;
                     const int src = u < 64 ? u : 63;
                     c[v] = __shfl(cl, src);
@@ -253,9 +268,10 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                     if (!(in_group && u < cnt)) s[v] = 0.0f;
                 }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) x[v] = (lane_ok && s[v] != 0.0f) ? R[(int64_t)c[v] * F + quad] : f4(0.0f);
+                for (int v = 0; v < kPieceUnroll; ++v)
+                    x[v] = (lane_ok && s[v] != 0.0f) ? R[(int64_t)c[v] * F + quad] : f4(0.0f);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) fma4(s[v], x[v], acc);
+                for (int v = 0; v < kPieceUnroll; ++v) fma4(s[v], x[v], acc);
             }
             for (; r < rounds; ++r) {
                 const int u = r * K + gi;
@@ -279,6 +295,100 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
     }
 }
 
+// Row epilogue shared by the row and heavy-row kernels: w_i = sigma (L R_j)_i
+// - tau R_{j-1}[i], stored; returns the FP64 products R_j[i] * w_i in s1.
+template <int MODE>
+__device__ __forceinline__ void row_epilogue(int64_t i, const float4& acc, const float* __restrict__ diag,
+                                             const float4* __restrict__ R, const float4* __restrict__ Rp,
+                                             float4* __restrict__ W, const float4& sg, const float4& tp,
+                                             int has_prev, int F, int quad, double (&s1)[4]) {
+    const float4 ri = R[i * F + quad];
+    const float di = diag[i];
+    float4 lr;  // (L R_j)_i
+    if (MODE == SLAQ_LAP_NORMALIZED) {
+        lr.x = fmaf(-di, acc.x, ri.x);
+        lr.y = fmaf(-di, acc.y, ri.y);
+        lr.z = fmaf(-di, acc.z, ri.z);
+        lr.w = fmaf(-di, acc.w, ri.w);
+    } else {
+        lr.x = fmaf(di, ri.x, -acc.x);
+        lr.y = fmaf(di, ri.y, -acc.y);
+        lr.z = fmaf(di, ri.z, -acc.z);
+        lr.w = fmaf(di, ri.w, -acc.w);
+    }
+    float4 wi = make_float4(sg.x * lr.x, sg.y * lr.y, sg.z * lr.z, sg.w * lr.w);
+    if (has_prev) {
+        const float4 rq = Rp[i * F + quad];
+        wi.x = fmaf(-tp.x, rq.x, wi.x);
+        wi.y = fmaf(-tp.y, rq.y, wi.y);
+        wi.z = fmaf(-tp.z, rq.z, wi.z);
+        wi.w = fmaf(-tp.w, rq.w, wi.w);
+    }
+    W[i * F + quad] = wi;
+    // products of two floats are exact in double
+    s1[0] = fma((double)ri.x, (double)wi.x, s1[0]);
+    s1[1] = fma((double)ri.y, (double)wi.y, s1[1]);
+    s1[2] = fma((double)ri.z, (double)wi.z, s1[2]);
+    s1[3] = fma((double)ri.w, (double)wi.w, s1[3]);
+}
+
+// Heavy rows: one wave per row sums the row's pieces (all column ranges, the
+// K groups taking every K-th piece, then a fixed-order tree), then the row
+// epilogue.  Dot partials go to columns col0 + block of `part`.
+template <int MODE>
+__global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__ st,
+                                                  const int32_t* __restrict__ hrow,
+                                                  const int64_t* __restrict__ segoff, int64_t cap,
+                                                  const float4* __restrict__ P, const float* __restrict__ diag,
+                                                  const float4* __restrict__ R, const float4* __restrict__ Rp,
+                                                  float4* __restrict__ W, const float* __restrict__ coef,
+                                                  int has_prev, double* __restrict__ part, int nb, int col0, int F,
+                                                  int G, int K, int ld, int tile0, int TQ) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gi = lane / G, gl = lane % G;
+    const int tile = tile0 + (int)blockIdx.y;
+    const int quad = tile * TQ + gl;
+    const bool in_group = gi < K;
+    const bool lane_ok = in_group && quad < F;
+    const int64_t nh = st->n_heavy;
+    double s1[4] = {0.0, 0.0, 0.0, 0.0};
+    float4 sg = f4(0.0f), tp = f4(0.0f);
+    if (lane_ok) {
+        sg = load4(coef, quad);
+        if (has_prev) tp = load4(coef + ld, quad);
+    }
+    for (int64_t h = (int64_t)blockIdx.x * 4 + wave; h < nh; h += (int64_t)gridDim.x * 4) {
+        float4 acc = f4(0.0f);
+        int64_t idx = 0;  // position in the row's piece list (ranges in order)
+        for (int x = 0; x < kColRanges; ++x) {
+            const int64_t p0 = segoff[(int64_t)x * cap + h], p1 = segoff[(int64_t)x * cap + h + 1];
+            // first piece of this range owned by group gi
+            int64_t p = p0 + ((gi - idx) % K + K) % K;
+            for (; p + 3 * K < p1; p += 4 * K) {
+                float4 xv[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xv[v] = lane_ok ? P[(p + v * K) * F + quad] : f4(0.0f);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) add4(acc, xv[v]);
+            }
+            for (; p < p1; p += K)
+                if (lane_ok) add4(acc, P[p * F + quad]);
+            idx += p1 - p0;
+        }
+        for (int sd = 1; sd < K; sd <<= 1) {
+            const int src = lane + sd * G < 64 ? lane + sd * G : lane;
+            float4 o;
+            o.x = __shfl(acc.x, src);
+            o.y = __shfl(acc.y, src);
+            o.z = __shfl(acc.z, src);
+            o.w = __shfl(acc.w, src);
+            if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) add4(acc, o);
+        }
+        if (gi == 0 && lane_ok) row_epilogue<MODE>((int64_t)hrow[h], acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
+    }
+    block_reduce_store(s1, part, nb, F, G, K, ld, tile, TQ, col0);
+}
+
 // Every non-isolated row: w = sigma (L R_j)_i - tau R_{j-1}[i]; partial R_j.w.
 // A wave takes windows of 64 rows (row offsets loaded by its lanes at once);
 // group gi handles rows gi, gi+K, ... of the window.
@@ -287,22 +397,19 @@ __global__ void __launch_bounds__(256) spmm_rows(int64_t n, const int64_t* __res
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ w,
                                                  const float* __restrict__ diag,
-                                                 const GraphStats* __restrict__ st,
-                                                 const int32_t* __restrict__ hrow,
-                                                 const int64_t* __restrict__ hoff,
-                                                 const float4* __restrict__ P, int heavy_min,
+                                                 int heavy_min,
                                                  const float4* __restrict__ R,
                                                  const float4* __restrict__ Rp,
                                                  float4* __restrict__ W, const float* __restrict__ coef,
                                                  int has_prev, double* __restrict__ part, int nb, int F, int G,
-                                                 int K, int ld, int rw) {
+                                                 int K, int ld, int rw, int tile0, int TQ) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int gbase = gi * G;
-    const int quad = blockIdx.y * kQuadsPerTile + gl;
+    const int tile = tile0 + (int)blockIdx.y;
+    const int quad = tile * TQ + gl;
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
-    const int64_t nh = st->n_heavy;
 
     double s1[4] = {0.0, 0.0, 0.0, 0.0};
     float4 sg = f4(0.0f), tp = f4(0.0f);
@@ -324,59 +431,14 @@ __global__ void __launch_bounds__(256) spmm_rows(int64_t n, const int64_t* __res
             const int64_t s = __shfl(rs_l, src), e = __shfl(re_l, src);
             const int64_t i = r0 + t;
             if (!in_group || t >= rw || i >= n || e == s) continue;  // isolated: nothing stored
+            if (e - s >= heavy_min) continue;  // heavy rows: spmm_heavy
             float4 acc = f4(0.0f);
-            int64_t h = nh;
-            if (e - s >= heavy_min) {
-                h = heavy_index(hrow, nh, i);
-                if (h < nh && (int64_t)hrow[h] != i) h = nh;  // not in the plan: compute directly
-            }
-            if (h < nh) {
-                const int64_t p0 = hoff[h], p1 = hoff[h + 1];
-                int64_t p = p0;
-                for (; p + 4 <= p1; p += 4) {
-                    float4 x[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) x[v] = lane_ok ? P[(p + v) * F + quad] : f4(0.0f);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) add4(acc, x[v]);
-                }
-                for (; p < p1; ++p)
-                    if (lane_ok) add4(acc, P[p * F + quad]);
-            } else {
-                group_segment<MODE, WEIGHTED>(acc, s, e, gbase, gl, G, col, w, diag, R, F, quad, lane_ok);
-            }
+            group_segment<MODE, WEIGHTED>(acc, s, e, gbase, gl, G, col, w, diag, R, F, quad, lane_ok);
             if (!lane_ok) continue;
-            const float4 ri = R[i * F + quad];
-            const float di = diag[i];
-            float4 lr;  // (L R_j)_i
-            if (MODE == SLAQ_LAP_NORMALIZED) {
-                lr.x = fmaf(-di, acc.x, ri.x);
-                lr.y = fmaf(-di, acc.y, ri.y);
-                lr.z = fmaf(-di, acc.z, ri.z);
-                lr.w = fmaf(-di, acc.w, ri.w);
-            } else {
-                lr.x = fmaf(di, ri.x, -acc.x);
-                lr.y = fmaf(di, ri.y, -acc.y);
-                lr.z = fmaf(di, ri.z, -acc.z);
-                lr.w = fmaf(di, ri.w, -acc.w);
-            }
-            float4 wi = make_float4(sg.x * lr.x, sg.y * lr.y, sg.z * lr.z, sg.w * lr.w);
-            if (has_prev) {
-                const float4 rq = Rp[i * F + quad];
-                wi.x = fmaf(-tp.x, rq.x, wi.x);
-                wi.y = fmaf(-tp.y, rq.y, wi.y);
-                wi.z = fmaf(-tp.z, rq.z, wi.z);
-                wi.w = fmaf(-tp.w, rq.w, wi.w);
-            }
-            W[i * F + quad] = wi;
-            // products of two floats are exact in double
-            s1[0] = fma((double)ri.x, (double)wi.x, s1[0]);
-            s1[1] = fma((double)ri.y, (double)wi.y, s1[1]);
-            s1[2] = fma((double)ri.z, (double)wi.z, s1[2]);
-            s1[3] = fma((double)ri.w, (double)wi.w, s1[3]);
+            row_epilogue<MODE>(i, acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
         }
     }
-    block_reduce_store(s1, part, nb, F, G, K, ld);
+    block_reduce_store(s1, part, nb, F, G, K, ld, tile, TQ);
 }
 
 // R_{j+1} = w - a_j R_j on non-isolated rows (stored when `store`), partial
@@ -385,10 +447,11 @@ __global__ void __launch_bounds__(256) update(int64_t n, const float* __restrict
                                               const float4* __restrict__ W, const float4* __restrict__ R,
                                               const float* __restrict__ coef, int store,
                                               float4* __restrict__ Rn, double* __restrict__ part, int nb,
-                                              int F, int G, int K, int ld, int rw) {
+                                              int F, int G, int K, int ld, int rw, int tile0, int TQ) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
-    const int quad = blockIdx.y * kQuadsPerTile + gl;
+    const int tile = tile0 + (int)blockIdx.y;
+    const int quad = tile * TQ + gl;
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
     double s2[4] = {0.0, 0.0, 0.0, 0.0};
@@ -419,7 +482,7 @@ __global__ void __launch_bounds__(256) update(int64_t n, const float* __restrict
             s2[3] = fma((double)r.w, (double)r.w, s2[3]);
         }
     }
-    block_reduce_store(s2, part, nb, F, G, K, ld);
+    block_reduce_store(s2, part, nb, F, G, K, ld, tile, TQ);
 }
 
 // ---------------------------------------------------------- finalize ------
@@ -492,7 +555,7 @@ __global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ par
 
 // ------------------------------------------------------------ layout ------
 struct Layout {
-    int ld, F, G, K, ntiles, nb_rows, nb_upd, piece_blocks, rw;
+    int ld, F, G, K, ntiles, TQ, Gu, Ku, ntiles_u, nb_rows, nb_upd, piece_blocks, rw, nb_heavy;
     int64_t max_pieces;
     size_t off_r[3], off_p, off_part1, off_part2, off_ps, off_coef, total;
 };
@@ -515,9 +578,20 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     Layout L{};
     L.ld = lanczos_ld(nv);
     L.F = L.ld / 4;
-    L.G = L.F < kQuadsPerTile ? L.F : kQuadsPerTile;
+    // probe tiles of the gather kernels, run one after another (a tile's
+    // gathered rows are narrower and stay in cache longer, but every nonzero
+    // is visited once per tile; on R-MAT scale 22 with nv = 100 one tile is
+    // fastest, so the default is one tile of up to 64 quads)
+    int tq = g->tile_quads > 0 ? g->tile_quads : kQuadsPerTile;
+    if (tq > kQuadsPerTile) tq = kQuadsPerTile;
+    if (tq > L.F) tq = L.F;
+    L.TQ = tq;
+    L.G = tq;
     L.K = 64 / L.G;
-    L.ntiles = (L.F + kQuadsPerTile - 1) / kQuadsPerTile;
+    L.ntiles = (L.F + tq - 1) / tq;
+    L.Gu = L.F < kQuadsPerTile ? L.F : kQuadsPerTile;
+    L.Ku = 64 / L.Gu;
+    L.ntiles_u = (L.F + kQuadsPerTile - 1) / kQuadsPerTile;
     // rows per wave window: up to 64, fewer on small graphs so that the
     // windows still cover every resident wave (never fewer than K)
     const int64_t target_waves = 8192;
@@ -534,12 +608,13 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     const int cap_u = upd_cap < kRowBlocks ? upd_cap : kRowBlocks;
     L.nb_rows = (int)(nb < cap_r ? nb : cap_r);
     L.nb_upd = (int)(nb < cap_u ? nb : cap_u);
-    // pieces <= nnz/piece + one partial piece per heavy row
+    // pieces <= nnz/piece + one partial piece per (heavy row, column range)
     int64_t heavy_cap = g->nnz / g->heavy_min;
     if (heavy_cap > g->n) heavy_cap = g->n;
-    L.max_pieces = g->nnz / g->piece + heavy_cap;
+    L.max_pieces = g->nnz / g->piece + kColRanges * heavy_cap;
     int64_t pb = (L.max_pieces + 3) / 4;
-    L.piece_blocks = (int)(pb < kPieceBlocks ? (pb > 0 ? pb : 1) : kPieceBlocks);
+    pb = pb < kPieceBlocks ? (pb > 0 ? pb : 1) : kPieceBlocks;
+    L.piece_blocks = (int)((pb + kColRanges - 1) / kColRanges * kColRanges);  // a multiple of the ranges
     const size_t vec = align_up((size_t)g->n * L.ld * sizeof(float), 256);
     size_t off = 0;
     for (int b = 0; b < 3; ++b) {
@@ -548,8 +623,13 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     }
     L.off_p = off;
     off += align_up((size_t)L.max_pieces * L.ld * sizeof(float), 256);
+    // heavy-row epilogue grid: one wave per heavy row, at most 1024 blocks
+    {
+        int64_t hb = (heavy_cap + 3) / 4;
+        L.nb_heavy = (int)(hb < 1 ? 1 : (hb > 1024 ? 1024 : hb));
+    }
     L.off_part1 = off;
-    off += align_up((size_t)L.ld * L.nb_rows * sizeof(double), 256);
+    off += align_up((size_t)L.ld * (L.nb_rows + L.nb_heavy) * sizeof(double), 256);
     L.off_part2 = off;
     off += align_up((size_t)L.ld * L.nb_upd * sizeof(double), 256);
     L.off_ps = off;
@@ -630,28 +710,45 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
 
     int cur = 0, prev = 1;
     const int wbuf = 2;
+    const int64_t cap = g->max_heavy > 0 ? g->max_heavy : 1;
+    const int nbp = L.nb_rows + L.nb_heavy;
     for (int j = 1; j <= m; ++j) {
-        if (L.max_pieces > 0) {
-            SLAQ_TIMED("spmm_pieces", st,
-                       SLAQ_DISPATCH(mode, weighted, spmm_pieces, dim3(L.piece_blocks, L.ntiles), dim3(256), 0, st,
-                                     g->stats, g->hrow, g->hoff, g->row_ptr, g->col_idx, g->weights, g->diag,
-                                     Rb[cur], P, L.F, L.G, L.K, g->piece));
+        const int hp = j > 1 ? 1 : 0;
+        for (int tile = 0; tile < L.ntiles; ++tile) {
+            if (L.max_pieces > 0) {
+                SLAQ_TIMED("spmm_pieces", st,
+                           SLAQ_DISPATCH(mode, weighted, spmm_pieces, dim3(L.piece_blocks, 1), dim3(256), 0, st,
+                                         g->stats, g->segk, g->segoff, cap, g->col_idx, g->weights, g->diag, Rb[cur], P,
+                                         L.F, L.G, L.K, g->piece, tile, L.TQ));
+                SLAQ_LAUNCHED();
+            }
+            SLAQ_TIMED("spmm_rows", st,
+                       SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st, g->n,
+                                     g->row_ptr, g->col_idx, g->weights, g->diag, g->heavy_min, Rb[cur], Rb[prev],
+                                     Rb[wbuf], coef, hp, part1, nbp, L.F, L.G, L.K, L.ld, L.rw, tile, L.TQ));
             SLAQ_LAUNCHED();
+            {  // always launched: its blocks write their (zero) dot partials even without heavy rows
+                SLAQ_TIMED("spmm_heavy", st, {
+                    if (mode == SLAQ_LAP_NORMALIZED)
+                        hipLaunchKernelGGL(spmm_heavy<SLAQ_LAP_NORMALIZED>, dim3(L.nb_heavy, 1), dim3(256), 0, st,
+                                           g->stats, g->hrow, g->segoff, cap, P, g->diag, Rb[cur], Rb[prev], Rb[wbuf],
+                                           coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
+                    else
+                        hipLaunchKernelGGL(spmm_heavy<SLAQ_LAP_COMBINATORIAL>, dim3(L.nb_heavy, 1), dim3(256), 0, st,
+                                           g->stats, g->hrow, g->segoff, cap, P, g->diag, Rb[cur], Rb[prev], Rb[wbuf],
+                                           coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
+                });
+                SLAQ_LAUNCHED();
+            }
         }
-        SLAQ_TIMED("spmm_rows", st,
-                   SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, L.ntiles), dim3(kSpmmBlock), 0, st,
-                                 g->n, g->row_ptr, g->col_idx, g->weights, g->diag, g->stats, g->hrow, g->hoff, P,
-                                 g->heavy_min, Rb[cur], Rb[prev], Rb[wbuf], coef, j > 1 ? 1 : 0, part1, L.nb_rows,
-                                 L.F, L.G, L.K, L.ld, L.rw));
-        SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
-                   hipLaunchKernelGGL(finalize_a, dim3(nv), dim3(256), 0, st, part1, L.nb_rows, L.ld, m, j,
+                   hipLaunchKernelGGL(finalize_a, dim3(nv), dim3(256), 0, st, part1, nbp, L.ld, m, j,
                                       g->stats, ps, alpha, coef));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("update", st,
-                   hipLaunchKernelGGL(update, dim3(L.nb_upd, L.ntiles), dim3(kSpmmBlock), 0, st, g->n, g->diag,
-                                      Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F, L.G,
-                                      L.K, L.ld, L.rw));
+                   hipLaunchKernelGGL(update, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->n, g->diag,
+                                      Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F, L.Gu,
+                                      L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
                    hipLaunchKernelGGL(finalize_b, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,

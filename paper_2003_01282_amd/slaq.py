@@ -37,6 +37,7 @@ SIGNATURES = {
                         ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
     "slaq_graph_destroy": [_vp],
     "slaq_graph_set_schedule": [_vp, _int, _int, _vp],
+    "slaq_graph_set_tile": [_vp, _int],
     "slaq_graph_schedule": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
                             ctypes.POINTER(_i64)],
     "slaq_lanczos_workspace": [_vp, _int, _int, ctypes.POINTER(_sz)],
@@ -146,6 +147,9 @@ class Graph:
 
     def set_schedule(self, heavy_min, piece, stream=None):
         _check(lib().slaq_graph_set_schedule(self.handle, heavy_min, piece, _stream(stream)))
+
+    def set_tile(self, tile_quads):
+        _check(lib().slaq_graph_set_tile(self.handle, tile_quads))
 
     def schedule(self):
         hm, pc, nh, npc = _int(), _int(), _i64(), _i64()

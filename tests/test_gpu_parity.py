@@ -104,7 +104,7 @@ def test_degenerate_graphs(case):
     np.testing.assert_allclose(gpu["tau2"].sum(axis=1), 1.0, atol=1e-9)
 
 
-@pytest.mark.parametrize("heavy_min,piece", [(32, 64), (256, 512), (64, 1024), (100000, 64)])
+@pytest.mark.parametrize("heavy_min,piece", [(128, 64), (256, 512), (128, 1024), (100000, 64)])
 def test_row_schedules(heavy_min, piece):
     # every schedule computes the same recurrence; heavy rows with partial
     # pieces, rows just below / above the threshold, no heavy rows at all
@@ -117,7 +117,15 @@ def test_row_schedules(heavy_min, piece):
     deg = np.diff(csr.row_ptr)
     heavy = deg >= heavy_min
     assert sch["n_heavy"] == int(heavy.sum())
-    assert sch["n_pieces"] == int(((deg[heavy] + piece - 1) // piece).sum())
+    # pieces: every heavy row is cut at the 8 column-id boundaries of equal nnz
+    # mass (first id whose row offset reaches nnz//8 * x), then into pieces
+    bnd = [0] + [int(np.searchsorted(csr.row_ptr, csr.nnz // 8 * x, side="left")) for x in range(1, 8)] + [csr.n]
+    expect = 0
+    for r in np.flatnonzero(heavy):
+        cols = csr.col_idx[csr.row_ptr[r]:csr.row_ptr[r + 1]]
+        lens = np.diff(np.searchsorted(cols, bnd[1:8], side="left"), prepend=0, append=cols.size)
+        expect += int(((lens + piece - 1) // piece).sum())
+    assert sch["n_pieces"] == expect
     a, b, s = S.lanczos(g, 24, 15, 31)
     th, w2 = S.ritz(a, b, s)
     tt = torch.from_numpy(T256).cuda()
@@ -128,6 +136,21 @@ def test_row_schedules(heavy_min, piece):
     np.testing.assert_allclose(a.cpu().numpy(), ora["alpha"], rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(b.cpu().numpy(), ora["beta"], rtol=1e-5, atol=1e-6)
     assert_signature_parity(gpu, ora, csr.n, f"schedule {heavy_min}/{piece}")
+
+
+@pytest.mark.parametrize("tile_quads", [0, 25, 7, 1])
+def test_probe_tiles(tile_quads):
+    # the gather kernels run once per probe tile; every tiling gives the same
+    # recurrence (auto = two tiles of 13 and 12 quads for nv = 100)
+    header(f"probe tiles {tile_quads}")
+    csr = inputs.chung_lu(6000, 30000, 2.5, seed=12)
+    rp, ci = S.to_device(csr)
+    g = S.build_graph(rp, ci)
+    g.set_tile(tile_quads)
+    a, b, s = S.lanczos(g, 100, 12, 77)
+    ora = oracle_run(csr, 100, 12, 77, T256[::16])
+    np.testing.assert_allclose(a.cpu().numpy(), ora["alpha"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(b.cpu().numpy(), ora["beta"], rtol=1e-5, atol=1e-6)
 
 
 def test_weighted_graph():
