@@ -279,3 +279,48 @@ def closure_graph_device(idx, seed=0, n_lo=1_000, n_hi=100_000, mean_degree=10.0
         e = torch.zeros(0, dtype=torch.int64, device=device)
         return _csr_from_pairs_torch(n, e, e)
     return _csr_from_pairs_torch(n, torch.cat(us), torch.cat(vs))
+
+
+def rmat_device(scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=0, device="cuda", chunk_log2=27):
+    """Device R-MAT (same recipe as rmat; torch's RNG, so not the same draws):
+    n = 2^scale, edge_factor * n samples drawn in chunks of 2^chunk_log2,
+    self-loops and duplicates dropped, symmetrized.  Returns (row_ptr int64,
+    col_idx int32) device tensors."""
+    import torch
+    n = 1 << scale
+    e = edge_factor * n
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(_rng(seed, 8).integers(0, 2**62)))
+    ab, abc = a + b, a + b + c
+    keys = []
+    for start in range(0, e, 1 << chunk_log2):
+        cnt = min(1 << chunk_log2, e - start)
+        src = torch.zeros(cnt, dtype=torch.int64, device=device)
+        dst = torch.zeros(cnt, dtype=torch.int64, device=device)
+        for _ in range(scale):
+            r = torch.rand(cnt, dtype=torch.float32, device=device, generator=gen)
+            src = (src << 1) | (r >= ab).to(torch.int64)
+            dst = (dst << 1) | (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64)
+            del r
+        keep = src != dst
+        lo = torch.minimum(src[keep], dst[keep])
+        hi = torch.maximum(src[keep], dst[keep])
+        del src, dst, keep
+        keys.append(torch.unique(lo * n + hi))
+        del lo, hi
+    key = torch.unique(torch.cat(keys))
+    del keys
+    lo = key // n
+    hi = key - lo * n
+    del key
+    both = torch.cat([lo * n + hi, hi * n + lo])
+    del lo, hi
+    both, _ = torch.sort(both)
+    rows = both // n
+    cols = (both - rows * n).to(torch.int32)
+    del both
+    counts = torch.bincount(rows, minlength=n)
+    del rows
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return row_ptr, cols
