@@ -61,8 +61,11 @@ enum { SLAQ_LAP_NORMALIZED = 0, SLAQ_LAP_COMBINATORIAL = 1 };
  * wave w_t = Re tr exp(-itL) = sum_i cos(t lambda_i). */
 enum { SLAQ_SIG_HEAT = 0, SLAQ_SIG_WAVE = 1 };
 
-/* slaq_build_graph flags */
-enum { SLAQ_FLAG_CHECK = 1u };
+/* slaq_build_graph flags.  SLAQ_FLAG_RELABEL / SLAQ_FLAG_NO_RELABEL force
+ * the internal node relabelling on or off (default: on from
+ * SLAQ_RELABEL_MIN_NNZ stored entries up); setting both is an error. */
+enum { SLAQ_FLAG_CHECK = 1u, SLAQ_FLAG_RELABEL = 2u, SLAQ_FLAG_NO_RELABEL = 4u };
+enum { SLAQ_RELABEL_MIN_NNZ = 1 << 22 };
 
 /* Size limits of this build. */
 enum { SLAQ_MAX_PROBES = 4096, SLAQ_MAX_STEPS = 64 };
@@ -83,7 +86,20 @@ slaq_status slaq_graph_scratch_bytes(int64_t n, int64_t nnz, size_t* bytes);
  * dinv_out and scratch must stay valid and unchanged until
  * slaq_graph_destroy.  With SLAQ_FLAG_CHECK the call validates the CSR
  * (monotone row_ptr, columns in range, symmetric pattern and weights,
- * positive finite weights) and waits for the result. */
+ * positive finite weights) and waits for the result.
+ *
+ * Relabelling (a storage order only; every result is a function of the
+ * graph and the probes, which stay keyed by the caller's node ids): the
+ * handle keeps its own copy of the CSR in scratch whose nodes are ordered by
+ * decreasing row length (stable, i.e. ties in caller id order; rows are
+ * bucketed exactly below 1024 entries and by 16 steps per octave above),
+ * isolated nodes dropped, and rank r of the n_act non-isolated nodes placed
+ * at label base(r mod 8) + r div 8 with base(x) = x q + min(x, n_act mod 8),
+ * q = n_act div 8: each eighth of the label space holds every eighth node of
+ * the degree order, so the eight column ranges of the row schedule carry
+ * near-equal nonzero mass and each range stores its hot rows together.
+ * Each relabelled row lists its entries range by range, in caller order
+ * within a range.  Without relabelling the caller's CSR is used as is. */
 slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr,
                              const int32_t* col_idx, const float* weights,
                              int laplacian, unsigned flags, float* dinv_out,
@@ -97,8 +113,9 @@ slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* tr
                             int64_t* n_isolated, double* max_degree);
 
 /* Row schedule of the SpMM.  Rows with at least heavy_min nonzeros are cut
- * at the 8 column-id boundaries of equal nnz mass (the first id whose row
- * offset reaches nnz/8 * x) and each part into pieces of at most `piece`
+ * at 8 column-label boundaries (relabelled: the range starts base(x); else
+ * the first id whose row offset reaches nnz/8 * x, i.e. equal nnz mass) and
+ * each part into pieces of at most `piece`
  * nonzeros that separate waves reduce in parallel; the pieces of column range
  * x run on workgroups b with b % 8 == x, i.e. one XCD, so that XCD's L2 holds
  * only that range's rows (defaults 256 and 512; heavy_min >= 128, piece a
@@ -116,6 +133,16 @@ slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int6
  * every nonzero once per tile.  0 (default) = tiles of 64 words (256 probes).
  * Changes the workspace size. */
 slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads);
+
+/* Internal storage order of the handle (waits for the build's stream).
+ * relabeled: 1 if the handle relabelled its nodes; n_rows: rows of the
+ * internal CSR (n_act when relabelled, else n).  perm (int32[n]), row_ptr
+ * (int64[n + 1]) and col_idx (int32[nnz]) are caller device buffers that
+ * receive the internal label -> caller id map (labels >= n_rows: the isolated
+ * nodes in caller order; identity without relabelling) and the internal
+ * CSR (rows >= n_rows empty).  Any pointer may be NULL. */
+slaq_status slaq_graph_internal(slaq_graph_t g, int* relabeled, int64_t* n_rows, int32_t* perm,
+                                int64_t* row_ptr, int32_t* col_idx);
 
 /* Frees the host handle (never caller memory). */
 slaq_status slaq_graph_destroy(slaq_graph_t g);

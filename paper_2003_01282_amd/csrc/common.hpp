@@ -47,6 +47,7 @@ struct GraphStats {
     long long n_isolated;  // #{i : D_ii = 0}
     long long n_heavy;     // rows split into pieces (degree >= heavy_min)
     long long n_pieces;    // total pieces of the heavy rows
+    long long n_rows;      // rows of the internal CSR (n_act when relabelled, else n)
     unsigned int check;    // SLAQ_FLAG_CHECK findings (bit mask, see graph.hip)
     unsigned int pad;
 };
@@ -73,16 +74,26 @@ constexpr int kMinPiece = 64;
 // i.e. on one XCD, whose L2 then holds only that range's hot rows.
 constexpr int kColRanges = 8;
 
+// Relabelling: nodes are counting-sorted by row-length bucket (exact below
+// 1024, 16 buckets per octave above; lengths < 2^31), in chunks of
+// kSortChunk caller ids per workgroup.
+constexpr int kDegBuckets = 1024 + 16 * 21;
+constexpr int kSortChunk = 4096;
+
 }  // namespace slaq
 
 struct slaq_graph_s {
     int64_t n;
     int64_t nnz;
+    // internal CSR the kernels read: the caller's, or its relabelled copy in scratch
     const int64_t* row_ptr;
     const int32_t* col_idx;
     const float* weights;   // NULL = unweighted
     int laplacian;          // SLAQ_LAP_*
-    float* diag;            // dinv (normalized) or degree (combinatorial); 0 <=> isolated
+    float* diag;            // per internal row: dinv (normalized) or degree (combinatorial); 0 <=> no data
+    const int32_t* perm;    // internal label -> caller id (NULL = identity)
+    int relabeled;
+    float* dinv_out;        // caller's diagonal scale, caller order
     slaq::GraphStats* stats;
     slaq::BuildPartial* partials;
     long long* blockcounts;  // [nplan] heavy rows, pieces per plan block, then offsets
@@ -104,6 +115,31 @@ namespace slaq {
 
 // Builds (or rebuilds) the heavy-row plan of g on `st` with its heavy_min/piece.
 slaq_status build_plan(slaq_graph_s* g, hipStream_t st);
+
+// Exclusive scan of in[0, len) into out (fixed-order, blocks of 1024);
+// bsum holds ceil(len / 1024) partials.  The total goes to *total_a and
+// *total_b when they are non-NULL.
+slaq_status exclusive_scan(const long long* in, int64_t len, int64_t* out, long long* bsum, long long* total_a,
+                           int64_t* total_b, hipStream_t st);
+
+// Scratch arrays of the relabelled CSR (see relabel.hip).
+struct RelabelBuffers {
+    int32_t* perm;       // [n] label -> caller id
+    int32_t* inv;        // [n] caller id -> label
+    int64_t* row_ptr;    // [n + 1]
+    int32_t* col;        // [nnz]
+    float* w;            // [nnz]
+    float* diag;         // [n]
+    long long* len;      // [n + 1] row lengths before the scan
+    long long* sort_cnt; // [kDegBuckets * chunks]
+    int64_t* sort_off;   // [kDegBuckets * chunks]
+    long long* bsum;     // scan partials
+};
+
+// Relabels the caller's CSR into B (sets st->n_rows and the range bounds).
+slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp, const int32_t* col,
+                          const float* w, const float* diag_caller, GraphStats* st, int64_t* bounds,
+                          hipStream_t stream);
 
 // ------------------------------------------------------- Lanczos layout ----
 // Vector blocks are row-major [n][ld], ld = nv rounded up to a multiple of 4

@@ -110,6 +110,7 @@ __global__ void __launch_bounds__(256) stats_kernel(int64_t n, int nparts, int l
         st->sum_degree = ssum[0];
         st->n_isolated = (long long)n - snz[0];
         st->trace = laplacian == SLAQ_LAP_NORMALIZED ? (double)snz[0] : ssum[0];
+        st->n_rows = n;  // the relabelling lowers it to n_act
         st->check = 0u;
     }
 }
@@ -318,12 +319,19 @@ __global__ void __launch_bounds__(256) seg_count(int64_t cap, const GraphStats* 
     }
 }
 
-// exclusive scan of cnt[0..len) in place, len = kColRanges * cap, blocks of 1024
-__global__ void __launch_bounds__(1024) seg_scan_blocks(int64_t len, const long long* __restrict__ cnt,
-                                                        long long* __restrict__ bsum) {
+__global__ void __launch_bounds__(256) iota_kernel(int64_t n, int32_t* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = (int32_t)i;
+}
+
+// ------------------------------------------------ exclusive scan (int64) ----
+// Three fixed-order passes: per-block sums, one-block scan of the sums, and
+// per-block scans offset by them.
+__global__ void __launch_bounds__(1024) scan_blocks(int64_t len, const long long* __restrict__ in,
+                                                    long long* __restrict__ bsum) {
     __shared__ long long red[1024];
     const int64_t i = blockIdx.x * 1024LL + threadIdx.x;
-    red[threadIdx.x] = i < len ? cnt[i] : 0;
+    red[threadIdx.x] = i < len ? in[i] : 0;
     __syncthreads();
     for (int off = 512; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
@@ -332,8 +340,8 @@ __global__ void __launch_bounds__(1024) seg_scan_blocks(int64_t len, const long 
     if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
 }
 
-__global__ void __launch_bounds__(1024) seg_scan_top(int64_t nb, long long* __restrict__ bsum,
-                                                     GraphStats* __restrict__ st, int64_t* __restrict__ total_out) {
+__global__ void __launch_bounds__(1024) scan_top(int64_t nb, long long* __restrict__ bsum,
+                                                 long long* __restrict__ total_a, int64_t* __restrict__ total_b) {
     const int t = threadIdx.x;
     const int64_t per = (nb + 1023) / 1024;
     const int64_t b0 = t * per, b1 = b0 + per < nb ? b0 + per : nb;
@@ -355,18 +363,17 @@ __global__ void __launch_bounds__(1024) seg_scan_top(int64_t nb, long long* __re
         run += v;
     }
     if (t == 1023) {
-        st->n_pieces = sh[1023];
-        *total_out = sh[1023];
+        if (total_a) *total_a = sh[1023];
+        if (total_b) *total_b = sh[1023];
     }
 }
 
-__global__ void __launch_bounds__(1024) seg_scan_apply(int64_t len, const long long* __restrict__ cnt,
-                                                       const long long* __restrict__ boff,
-                                                       int64_t* __restrict__ segoff) {
+__global__ void __launch_bounds__(1024) scan_apply(int64_t len, const long long* __restrict__ in,
+                                                   const long long* __restrict__ boff, int64_t* __restrict__ out) {
     __shared__ long long sh[1024];
     const int t = threadIdx.x;
     const int64_t i = blockIdx.x * 1024LL + t;
-    const long long v = i < len ? cnt[i] : 0;
+    const long long v = i < len ? in[i] : 0;
     sh[t] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -375,13 +382,26 @@ __global__ void __launch_bounds__(1024) seg_scan_apply(int64_t len, const long l
         sh[t] += a;
         __syncthreads();
     }
-    if (i < len) segoff[i] = boff[blockIdx.x] + sh[t] - v;
+    if (i < len) out[i] = boff[blockIdx.x] + sh[t] - v;
+}
+
+slaq_status exclusive_scan(const long long* in, int64_t len, int64_t* out, long long* bsum, long long* total_a,
+                           int64_t* total_b, hipStream_t st) {
+    const int64_t nb = (len + 1023) / 1024;
+    if (nb == 0) return SLAQ_OK;
+    hipLaunchKernelGGL(scan_blocks, dim3((unsigned)nb), dim3(1024), 0, st, len, in, bsum);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, st, nb, bsum, total_a, total_b);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(1024), 0, st, len, in, bsum, out);
+    SLAQ_LAUNCHED();
+    return SLAQ_OK;
 }
 
 struct ScratchLayout {
     size_t off_stats, off_part, off_counts, off_hrow, off_hoff, off_bounds, off_segk, off_cnt, off_segoff, off_bsum,
-        total;
-    int64_t nplan, max_heavy, seg_blocks;
+        off_perm, off_inv, off_rp2, off_col2, off_w2, off_diag2, off_len, off_sortcnt, off_sortoff, total;
+    int64_t nplan, max_heavy, sort_chunks;
 };
 
 static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
@@ -389,29 +409,38 @@ static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     L.nplan = (n + kPlanBlock - 1) / kPlanBlock;
     L.max_heavy = nnz / kMinHeavyMin;
     if (L.max_heavy > n) L.max_heavy = n;
+    L.sort_chunks = (n + kSortChunk - 1) / kSortChunk;
     size_t off = 0;
-    L.off_stats = off;
-    off += align_up(sizeof(GraphStats), 256);
-    L.off_part = off;
-    off += align_up(sizeof(BuildPartial) * kBuildBlocks, 256);
-    L.off_counts = off;
-    off += align_up(sizeof(long long) * 4 * (size_t)L.nplan, 256);
-    L.off_hrow = off;
-    off += align_up(sizeof(int32_t) * (size_t)(L.max_heavy + 1), 256);
-    L.off_hoff = off;
-    off += align_up(sizeof(int64_t) * (size_t)(L.max_heavy + 1), 256);
+    auto take = [&off](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes, 256);
+        return o;
+    };
     const size_t cap = (size_t)(L.max_heavy > 0 ? L.max_heavy : 1);
-    L.off_bounds = off;
-    off += align_up(sizeof(int64_t) * (kColRanges + 1), 256);
-    L.off_segk = off;
-    off += align_up(sizeof(int64_t) * (kColRanges + 1) * cap, 256);
-    L.off_cnt = off;
-    off += align_up(sizeof(long long) * kColRanges * cap, 256);
-    L.off_segoff = off;
-    off += align_up(sizeof(int64_t) * (kColRanges * cap + 1), 256);
-    L.seg_blocks = (int64_t)((kColRanges * cap + 1023) / 1024);
-    L.off_bsum = off;
-    off += align_up(sizeof(long long) * (size_t)L.seg_blocks, 256);
+    const size_t sort_len = (size_t)kDegBuckets * (size_t)L.sort_chunks;
+    size_t scan_max = kColRanges * cap;
+    if (sort_len > scan_max) scan_max = sort_len;
+    if ((size_t)n + 1 > scan_max) scan_max = (size_t)n + 1;
+    L.off_stats = take(sizeof(GraphStats));
+    L.off_part = take(sizeof(BuildPartial) * kBuildBlocks);
+    L.off_counts = take(sizeof(long long) * 4 * (size_t)L.nplan);
+    L.off_hrow = take(sizeof(int32_t) * (size_t)(L.max_heavy + 1));
+    L.off_hoff = take(sizeof(int64_t) * (size_t)(L.max_heavy + 1));
+    L.off_bounds = take(sizeof(int64_t) * (kColRanges + 1));
+    L.off_segk = take(sizeof(int64_t) * (kColRanges + 1) * cap);
+    L.off_cnt = take(sizeof(long long) * kColRanges * cap);
+    L.off_segoff = take(sizeof(int64_t) * (kColRanges * cap + 1));
+    L.off_bsum = take(sizeof(long long) * ((scan_max + 1023) / 1024));
+    // relabelled CSR
+    L.off_perm = take(sizeof(int32_t) * (size_t)n);
+    L.off_inv = take(sizeof(int32_t) * (size_t)n);
+    L.off_rp2 = take(sizeof(int64_t) * ((size_t)n + 1));
+    L.off_col2 = take(sizeof(int32_t) * (size_t)nnz);
+    L.off_w2 = take(sizeof(float) * (size_t)nnz);
+    L.off_diag2 = take(sizeof(float) * (size_t)n);
+    L.off_len = take(sizeof(long long) * ((size_t)n + 1));
+    L.off_sortcnt = take(sizeof(long long) * sort_len);
+    L.off_sortoff = take(sizeof(int64_t) * sort_len);
     L.total = off;
     return L;
 }
@@ -431,19 +460,14 @@ slaq_status build_plan(slaq_graph_s* g, hipStream_t st) {
     // column-range segments and their pieces
     const int64_t cap = g->max_heavy > 0 ? g->max_heavy : 1;
     const int64_t len = kColRanges * cap;
-    const int64_t nb = (len + 1023) / 1024;
-    hipLaunchKernelGGL(xcd_bounds, dim3(1), dim3(64), 0, st, g->n, g->nnz, g->row_ptr, g->bounds);
-    SLAQ_LAUNCHED();
+    if (!g->relabeled) {  // relabelled graphs got their range starts from the relabelling
+        hipLaunchKernelGGL(xcd_bounds, dim3(1), dim3(64), 0, st, g->n, g->nnz, g->row_ptr, g->bounds);
+        SLAQ_LAUNCHED();
+    }
     hipLaunchKernelGGL(seg_count, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, cap, g->stats, g->hrow,
                        g->row_ptr, g->col_idx, g->bounds, g->piece, g->segk, g->segcnt);
     SLAQ_LAUNCHED();
-    hipLaunchKernelGGL(seg_scan_blocks, dim3((unsigned)nb), dim3(1024), 0, st, len, g->segcnt, g->scanbuf);
-    SLAQ_LAUNCHED();
-    hipLaunchKernelGGL(seg_scan_top, dim3(1), dim3(1024), 0, st, nb, g->scanbuf, g->stats, g->segoff + len);
-    SLAQ_LAUNCHED();
-    hipLaunchKernelGGL(seg_scan_apply, dim3((unsigned)nb), dim3(1024), 0, st, len, g->segcnt, g->scanbuf, g->segoff);
-    SLAQ_LAUNCHED();
-    return SLAQ_OK;
+    return exclusive_scan(g->segcnt, len, g->segoff, g->scanbuf, &g->stats->n_pieces, g->segoff + len, st);
 }
 
 }  // namespace slaq
@@ -475,7 +499,11 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     SLAQ_REQUIRE(nnz == 0 || col_idx, SLAQ_ERR_INVALID_ARG, "col_idx is NULL");
     SLAQ_REQUIRE(laplacian == SLAQ_LAP_NORMALIZED || laplacian == SLAQ_LAP_COMBINATORIAL,
                  SLAQ_ERR_INVALID_ARG, "unknown laplacian kind %d", laplacian);
-    SLAQ_REQUIRE((flags & ~(unsigned)SLAQ_FLAG_CHECK) == 0, SLAQ_ERR_INVALID_ARG, "unknown flags");
+    SLAQ_REQUIRE((flags & ~(unsigned)(SLAQ_FLAG_CHECK | SLAQ_FLAG_RELABEL | SLAQ_FLAG_NO_RELABEL)) == 0,
+                 SLAQ_ERR_INVALID_ARG, "unknown flags");
+    SLAQ_REQUIRE((flags & (SLAQ_FLAG_RELABEL | SLAQ_FLAG_NO_RELABEL)) !=
+                     (unsigned)(SLAQ_FLAG_RELABEL | SLAQ_FLAG_NO_RELABEL),
+                 SLAQ_ERR_INVALID_ARG, "SLAQ_FLAG_RELABEL and SLAQ_FLAG_NO_RELABEL both set");
     size_t need = 0;
     slaq_graph_scratch_bytes(n, nnz, &need);
     SLAQ_REQUIRE(scratch_bytes >= need, SLAQ_ERR_WORKSPACE, "graph scratch needs %zu bytes, got %zu",
@@ -518,6 +546,9 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(256), 0, st, n, blocks, laplacian, part, stats);
     SLAQ_LAUNCHED();
 
+    const bool relabel = (flags & SLAQ_FLAG_RELABEL) ||
+                         (!(flags & SLAQ_FLAG_NO_RELABEL) && nnz >= (int64_t)SLAQ_RELABEL_MIN_NNZ);
+
     slaq_graph_s* g = new (std::nothrow) slaq_graph_s;
     SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "out of host memory");
     g->blockcounts = (long long*)(base + SL.off_counts);
@@ -532,17 +563,44 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->heavy_min = kDefaultHeavyMin;
     g->piece = kDefaultPiece;
     g->tile_quads = 0;
-    g->row_ptr = row_ptr;
     g->n = n;
     g->nnz = nnz;
-    g->row_ptr = row_ptr;
-    g->col_idx = col_idx;
-    g->weights = weights;
     g->laplacian = laplacian;
-    g->diag = dinv_out;
+    g->dinv_out = dinv_out;
     g->stats = stats;
     g->partials = part;
     g->stream = st;
+    if (relabel) {
+        RelabelBuffers B;
+        B.perm = (int32_t*)(base + SL.off_perm);
+        B.inv = (int32_t*)(base + SL.off_inv);
+        B.row_ptr = (int64_t*)(base + SL.off_rp2);
+        B.col = (int32_t*)(base + SL.off_col2);
+        B.w = (float*)(base + SL.off_w2);
+        B.diag = (float*)(base + SL.off_diag2);
+        B.len = (long long*)(base + SL.off_len);
+        B.sort_cnt = (long long*)(base + SL.off_sortcnt);
+        B.sort_off = (int64_t*)(base + SL.off_sortoff);
+        B.bsum = g->scanbuf;
+        const slaq_status rs = relabel_build(B, n, row_ptr, col_idx, weights, dinv_out, stats, g->bounds, st);
+        if (rs != SLAQ_OK) {
+            delete g;
+            return rs;
+        }
+        g->row_ptr = B.row_ptr;
+        g->col_idx = B.col;
+        g->weights = weights ? B.w : nullptr;
+        g->diag = B.diag;
+        g->perm = B.perm;
+        g->relabeled = 1;
+    } else {
+        g->row_ptr = row_ptr;
+        g->col_idx = col_idx;
+        g->weights = weights;
+        g->diag = dinv_out;
+        g->perm = nullptr;
+        g->relabeled = 0;
+    }
     const slaq_status ps = build_plan(g, st);
     if (ps != SLAQ_OK) {
         delete g;
@@ -599,6 +657,34 @@ slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int6
         if (n_heavy) *n_heavy = hs.n_heavy;
         if (n_pieces) *n_pieces = hs.n_pieces;
     }
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_internal(slaq_graph_t g, int* relabeled, int64_t* n_rows, int32_t* perm,
+                                int64_t* row_ptr, int32_t* col_idx) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    hipStream_t st = g->stream;
+    if (relabeled) *relabeled = g->relabeled;
+    if (n_rows) {
+        GraphStats hs;
+        SLAQ_HIP(hipMemcpyAsync(&hs, g->stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+        SLAQ_HIP(hipStreamSynchronize(st));
+        *n_rows = hs.n_rows;
+    }
+    if (perm) {
+        if (g->perm) {
+            SLAQ_HIP(hipMemcpyAsync(perm, g->perm, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToDevice, st));
+        } else {
+            hipLaunchKernelGGL(iota_kernel, dim3(256), dim3(256), 0, st, g->n, perm);
+            SLAQ_LAUNCHED();
+        }
+    }
+    if (row_ptr)
+        SLAQ_HIP(hipMemcpyAsync(row_ptr, g->row_ptr, sizeof(int64_t) * (size_t)(g->n + 1), hipMemcpyDeviceToDevice, st));
+    if (col_idx && g->nnz > 0)
+        SLAQ_HIP(hipMemcpyAsync(col_idx, g->col_idx, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToDevice, st));
+    SLAQ_HIP(hipStreamSynchronize(st));
     return SLAQ_OK;
 }
 

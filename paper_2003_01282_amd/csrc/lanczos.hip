@@ -117,21 +117,25 @@ __global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double 
     }
 }
 
-// R_1[i][p] = +-1 (bit (p mod 64) of splitmix64(seed, 64 i + p div 64)) on
-// non-isolated rows; padding probes are 0.  One quad per thread, rows strided.
-__global__ void __launch_bounds__(256) probe_init(int64_t n, int nv, int F, int rows_per_sweep,
-                                                  uint64_t seed, const float* __restrict__ diag,
-                                                  float4* __restrict__ R) {
+// R_1[i][p] = +-1 (bit (p mod 64) of splitmix64(seed, 64 id + p div 64), id
+// the caller's id of internal row i) on rows with data; padding probes are 0.
+// One quad per thread, rows strided.
+__global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__ st, int nv, int F,
+                                                  int rows_per_sweep, uint64_t seed,
+                                                  const float* __restrict__ diag,
+                                                  const int32_t* __restrict__ perm, float4* __restrict__ R) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int quad = tid % F;
     const int64_t row0 = tid / F;
     if (row0 >= rows_per_sweep) return;
+    const int64_t n = st->n_rows;
     const int p0 = 4 * quad;
     const uint64_t word = (uint64_t)(p0 >> 6);
     const int bit0 = p0 & 63;
     for (int64_t i = row0; i < n; i += rows_per_sweep) {
         if (diag[i] == 0.0f) continue;
-        const uint64_t z = splitmix64(seed, 64ull * (uint64_t)i + word);
+        const uint64_t id = perm ? (uint64_t)perm[i] : (uint64_t)i;
+        const uint64_t z = splitmix64(seed, 64ull * id + word);
         float v[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -182,16 +186,6 @@ __device__ __forceinline__ void group_segment(float4& acc, int64_t k0, int64_t k
             if (lane_ok) fma4(s, R[(int64_t)c * F + quad], acc);
         }
     }
-}
-
-// index of row i in the increasing list hrow[0..nh)
-__device__ __forceinline__ int64_t heavy_index(const int32_t* __restrict__ hrow, int64_t nh, int64_t i) {
-    int64_t lo = 0, hi = nh;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((int64_t)hrow[mid] < i) lo = mid + 1; else hi = mid;
-    }
-    return lo;
 }
 
 // One wave per piece: P[p] = sum over the piece's nonzeros of scale * R_j[col].
@@ -393,7 +387,7 @@ __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__
 // A wave takes windows of 64 rows (row offsets loaded by its lanes at once);
 // group gi handles rows gi, gi+K, ... of the window.
 template <int MODE, bool WEIGHTED>
-__global__ void __launch_bounds__(256) spmm_rows(int64_t n, const int64_t* __restrict__ rp,
+__global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ st, const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ w,
                                                  const float* __restrict__ diag,
@@ -417,6 +411,7 @@ __global__ void __launch_bounds__(256) spmm_rows(int64_t n, const int64_t* __res
         sg = load4(coef, quad);
         if (has_prev) tp = load4(coef + ld, quad);
     }
+    const int64_t n = st->n_rows;
     const int rounds = (rw + K - 1) / K;
     const int64_t nwin = (n + rw - 1) / rw;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -443,7 +438,7 @@ __global__ void __launch_bounds__(256) spmm_rows(int64_t n, const int64_t* __res
 
 // R_{j+1} = w - a_j R_j on non-isolated rows (stored when `store`), partial
 // sums of ||R_{j+1}||^2.  Same wave/group layout as spmm_rows.
-__global__ void __launch_bounds__(256) update(int64_t n, const float* __restrict__ diag,
+__global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st, const float* __restrict__ diag,
                                               const float4* __restrict__ W, const float4* __restrict__ R,
                                               const float* __restrict__ coef, int store,
                                               float4* __restrict__ Rn, double* __restrict__ part, int nb,
@@ -457,6 +452,7 @@ __global__ void __launch_bounds__(256) update(int64_t n, const float* __restrict
     double s2[4] = {0.0, 0.0, 0.0, 0.0};
     float4 a = f4(0.0f);
     if (lane_ok) a = load4(coef + 2 * ld, quad);
+    const int64_t n = st->n_rows;
     const int rounds = (rw + K - 1) / K;
     const int64_t nwin = (n + rw - 1) / rw;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -705,7 +701,8 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
     SLAQ_LAUNCHED();
     int rps = 0;
     const int sgrid = sweep_grid(g->n, L.F, &rps);
-    hipLaunchKernelGGL(probe_init, dim3(sgrid), dim3(256), 0, st, g->n, nv, L.F, rps, seed, g->diag, Rb[0]);
+    hipLaunchKernelGGL(probe_init, dim3(sgrid), dim3(256), 0, st, g->stats, nv, L.F, rps, seed, g->diag, g->perm,
+                       Rb[0]);
     SLAQ_LAUNCHED();
 
     int cur = 0, prev = 1;
@@ -723,7 +720,7 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
                 SLAQ_LAUNCHED();
             }
             SLAQ_TIMED("spmm_rows", st,
-                       SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st, g->n,
+                       SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st, g->stats,
                                      g->row_ptr, g->col_idx, g->weights, g->diag, g->heavy_min, Rb[cur], Rb[prev],
                                      Rb[wbuf], coef, hp, part1, nbp, L.F, L.G, L.K, L.ld, L.rw, tile, L.TQ));
             SLAQ_LAUNCHED();
@@ -746,7 +743,7 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
                                       g->stats, ps, alpha, coef));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("update", st,
-                   hipLaunchKernelGGL(update, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->n, g->diag,
+                   hipLaunchKernelGGL(update, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->stats, g->diag,
                                       Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F, L.Gu,
                                       L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
         SLAQ_LAUNCHED();

@@ -16,6 +16,9 @@ SLAQ_LAP_COMBINATORIAL = 1
 SLAQ_SIG_HEAT = 0
 SLAQ_SIG_WAVE = 1
 SLAQ_FLAG_CHECK = 1
+SLAQ_FLAG_RELABEL = 2
+SLAQ_FLAG_NO_RELABEL = 4
+SLAQ_RELABEL_MIN_NNZ = 1 << 22
 SLAQ_MAX_PROBES = 4096
 SLAQ_MAX_STEPS = 64
 
@@ -36,6 +39,7 @@ SIGNATURES = {
     "slaq_graph_info": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                         ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
     "slaq_graph_destroy": [_vp],
+    "slaq_graph_internal": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_i64), _vp, _vp, _vp],
     "slaq_graph_set_schedule": [_vp, _int, _int, _vp],
     "slaq_graph_set_tile": [_vp, _int],
     "slaq_graph_schedule": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
@@ -157,6 +161,19 @@ class Graph:
                                          ctypes.byref(npc)))
         return {"heavy_min": hm.value, "piece": pc.value, "n_heavy": nh.value, "n_pieces": npc.value}
 
+    def internal(self):
+        """slaq_graph_internal -> dict(relabeled, n_rows, perm, row_ptr, col_idx)
+        (device tensors: label -> caller id, and the internal CSR)."""
+        dev = self._keep["row_ptr"].device
+        rel, nr = _int(), _i64()
+        perm = torch.empty(self.n, dtype=torch.int32, device=dev)
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        _check(lib().slaq_graph_internal(self.handle, ctypes.byref(rel), ctypes.byref(nr), _ptr(perm), _ptr(rp),
+                                         _ptr(ci)))
+        return {"relabeled": bool(rel.value), "n_rows": nr.value, "perm": perm, "row_ptr": rp,
+                "col_idx": ci[:self.nnz]}
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and _LIB is not None:
@@ -165,9 +182,10 @@ class Graph:
 
 
 def build_graph(row_ptr, col_idx, weights=None, laplacian=SLAQ_LAP_NORMALIZED, check=False, stream=None,
-                dinv=None, scratch=None):
+                dinv=None, scratch=None, relabel=None):
     """slaq_build_graph on device CSR tensors (int64 row_ptr, int32 col_idx,
-    optional float32 weights).  dinv / scratch may be passed preallocated."""
+    optional float32 weights).  dinv / scratch may be passed preallocated.
+    relabel: None = the library's size rule, True / False = forced."""
     _dev(row_ptr, torch.int64, "row_ptr")
     _dev(col_idx, torch.int32, "col_idx")
     if weights is not None:
@@ -182,8 +200,11 @@ def build_graph(row_ptr, col_idx, weights=None, laplacian=SLAQ_LAP_NORMALIZED, c
     if scratch is None:
         scratch = _empty_aligned(nbytes.value, dev)
     h = _vp()
+    flags = SLAQ_FLAG_CHECK if check else 0
+    if relabel is not None:
+        flags |= SLAQ_FLAG_RELABEL if relabel else SLAQ_FLAG_NO_RELABEL
     _check(lib().slaq_build_graph(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(weights), laplacian,
-                                  SLAQ_FLAG_CHECK if check else 0, _ptr(dinv), _ptr(scratch), scratch.numel(),
+                                  flags, _ptr(dinv), _ptr(scratch), scratch.numel(),
                                   _stream(stream), ctypes.byref(h)))
     keep = {"row_ptr": row_ptr, "col_idx": col_idx, "weights": weights, "dinv": dinv, "scratch": scratch}
     return Graph(h, n, nnz, laplacian, keep)
