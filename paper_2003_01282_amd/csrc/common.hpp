@@ -65,8 +65,8 @@ struct BuildPartial {
 // Row schedule of the SpMM: rows of degree >= heavy_min are cut into pieces of
 // at most `piece` nonzeros (a piece never crosses a row).  heavy_min and piece
 // are tunable (slaq_graph_set_schedule); these are the defaults and bounds.
-constexpr int kDefaultHeavyMin = 256;
-constexpr int kDefaultPiece = 512;
+constexpr int kDefaultHeavyMin = 128;
+constexpr int kDefaultPiece = 128;
 constexpr int kMinHeavyMin = 128;
 constexpr int kMinPiece = 64;
 // Heavy rows are also cut at kColRanges column-id boundaries of equal nnz
@@ -129,6 +129,7 @@ struct RelabelBuffers {
     int64_t* row_ptr;    // [n + 1]
     int32_t* col;        // [nnz]
     float* w;            // [nnz]
+    int32_t* tmp;        // [nnz] labels of long rows in caller order
     float* diag;         // [n]
     long long* len;      // [n + 1] row lengths before the scan
     long long* sort_cnt; // [kDegBuckets * chunks]

@@ -400,7 +400,7 @@ slaq_status exclusive_scan(const long long* in, int64_t len, int64_t* out, long 
 
 struct ScratchLayout {
     size_t off_stats, off_part, off_counts, off_hrow, off_hoff, off_bounds, off_segk, off_cnt, off_segoff, off_bsum,
-        off_perm, off_inv, off_rp2, off_col2, off_w2, off_diag2, off_len, off_sortcnt, off_sortoff, total;
+        off_perm, off_inv, off_rp2, off_col2, off_w2, off_tmp, off_diag2, off_len, off_sortcnt, off_sortoff, total;
     int64_t nplan, max_heavy, sort_chunks;
 };
 
@@ -437,6 +437,7 @@ static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     L.off_rp2 = take(sizeof(int64_t) * ((size_t)n + 1));
     L.off_col2 = take(sizeof(int32_t) * (size_t)nnz);
     L.off_w2 = take(sizeof(float) * (size_t)nnz);
+    L.off_tmp = take(sizeof(int32_t) * (size_t)nnz);
     L.off_diag2 = take(sizeof(float) * (size_t)n);
     L.off_len = take(sizeof(long long) * ((size_t)n + 1));
     L.off_sortcnt = take(sizeof(long long) * sort_len);
@@ -577,6 +578,7 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
         B.row_ptr = (int64_t*)(base + SL.off_rp2);
         B.col = (int32_t*)(base + SL.off_col2);
         B.w = (float*)(base + SL.off_w2);
+        B.tmp = (int32_t*)(base + SL.off_tmp);
         B.diag = (float*)(base + SL.off_diag2);
         B.len = (long long*)(base + SL.off_len);
         B.sort_cnt = (long long*)(base + SL.off_sortcnt);

@@ -23,8 +23,9 @@
 //   relabel_len    row lengths and diagonal scale in label order
 //   scan           row offsets of the relabelled CSR
 //   range bounds   base(x), x = 0..8
-//   relabel_rows   one wave per row: columns mapped to labels and listed range
-//                  by range (caller order within a range), weights alongside
+//   relabel_rows   one wave per row: columns mapped to labels (one gather
+//                  each) and listed range by range (caller order within a
+//                  range), weights alongside
 #include "common.hpp"
 
 namespace slaq {
@@ -132,13 +133,19 @@ __device__ __forceinline__ int range_of(int64_t c, const int64_t (&bnd)[kColRang
     return x;
 }
 
+// One wave per relabelled row.  Each caller column is mapped to its label
+// once (the gather inv[col] is the costly part: random 4-byte reads): rows of
+// at most 64 entries keep the labels in registers and are placed in one pass
+// from 8 ballots (one per range); longer rows park the labels, in caller
+// order, in `tmp` at the row's own offsets (coalesced), count per range, then
+// read them back and place them.
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(256) relabel_rows(const GraphStats* __restrict__ st, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ col, const float* __restrict__ w,
                                                     const int32_t* __restrict__ perm, const int32_t* __restrict__ inv,
                                                     const int64_t* __restrict__ bounds,
                                                     const int64_t* __restrict__ rp2, int32_t* __restrict__ col2,
-                                                    float* __restrict__ w2) {
+                                                    float* __restrict__ w2, int32_t* __restrict__ tmp) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt = (1ull << lane) - 1ull;
     const int64_t nr = st->n_rows;
@@ -147,16 +154,43 @@ __global__ void __launch_bounds__(256) relabel_rows(const GraphStats* __restrict
     for (int r = 0; r < kColRanges; ++r) bnd[r] = bounds[r];
     for (int64_t L = (int64_t)blockIdx.x * 4 + wave; L < nr; L += (int64_t)gridDim.x * 4) {
         const int64_t o = perm[L], s = rp[o], e = rp[o + 1];
+        const int64_t dst = rp2[L];
+        if (e - s <= 64) {
+            const int64_t k = s + lane;
+            int32_t c = 0;
+            int x = -1;
+            if (k < e) {
+                c = inv[col[k]];
+                x = range_of(c, bnd);
+            }
+            int64_t run = dst;
+#pragma unroll
+            for (int r = 0; r < kColRanges; ++r) {
+                const uint64_t mr = __ballot(x == r);
+                if (x == r) {
+                    const int64_t p = run + __popcll(mr & lt);
+                    col2[p] = c;
+                    if (WEIGHTED) w2[p] = w[k];
+                }
+                run += __popcll(mr);
+            }
+            continue;
+        }
         int64_t pos[kColRanges];
 #pragma unroll
         for (int r = 0; r < kColRanges; ++r) pos[r] = 0;
         for (int64_t k0 = s; k0 < e; k0 += 64) {
             const int64_t k = k0 + lane;
-            const int x = k < e ? range_of(inv[col[k]], bnd) : -1;
+            int x = -1;
+            if (k < e) {
+                const int32_t c = inv[col[k]];
+                tmp[dst + (k - s)] = c;
+                x = range_of(c, bnd);
+            }
 #pragma unroll
             for (int r = 0; r < kColRanges; ++r) pos[r] += __popcll(__ballot(x == r));
         }
-        int64_t run = rp2[L];
+        int64_t run = dst;
 #pragma unroll
         for (int r = 0; r < kColRanges; ++r) {
             const int64_t c = pos[r];
@@ -168,7 +202,7 @@ __global__ void __launch_bounds__(256) relabel_rows(const GraphStats* __restrict
             int32_t c = 0;
             int x = -1;
             if (k < e) {
-                c = inv[col[k]];
+                c = tmp[dst + (k - s)];
                 x = range_of(c, bnd);
             }
 #pragma unroll
@@ -210,10 +244,10 @@ slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp,
     if (rb < 1) rb = 1;
     if (w)
         hipLaunchKernelGGL(relabel_rows<true>, dim3((unsigned)rb), dim3(256), 0, stream, st, rp, col, w, B.perm, B.inv,
-                           bounds, B.row_ptr, B.col, B.w);
+                           bounds, B.row_ptr, B.col, B.w, B.tmp);
     else
         hipLaunchKernelGGL(relabel_rows<false>, dim3((unsigned)rb), dim3(256), 0, stream, st, rp, col, w, B.perm,
-                           B.inv, bounds, B.row_ptr, B.col, B.w);
+                           B.inv, bounds, B.row_ptr, B.col, B.w, B.tmp);
     SLAQ_LAUNCHED();
     return SLAQ_OK;
 }

@@ -120,7 +120,8 @@ def test_combinatorial_hub_graph():
         assert abs(gpu["vnge"] - ora["vnge"]) / abs(ora["vnge"]) <= 1e-3
         rel = np.abs(gpu["heat"][early] - ora["heat"][early]) / ora["heat"][early]
         assert rel.max() <= 1e-4
-    np.testing.assert_allclose(runs[0]["heat"], runs[1]["heat"], rtol=1e-3)
+    # heat counts nodes (h_0 = n): an absolute floor of 1e-4 for its decayed tail
+    np.testing.assert_allclose(runs[0]["heat"], runs[1]["heat"], rtol=1e-3, atol=1e-4)
 
 
 def test_relabelled_weighted():
