@@ -67,6 +67,10 @@ enum { SLAQ_SIG_HEAT = 0, SLAQ_SIG_WAVE = 1 };
 enum { SLAQ_FLAG_CHECK = 1u, SLAQ_FLAG_RELABEL = 2u, SLAQ_FLAG_NO_RELABEL = 4u };
 enum { SLAQ_RELABEL_MIN_NNZ = 1 << 22 };
 
+/* Precision of the Lanczos vectors (slaq_graph_set_precision).  The dot
+ * products, alpha, beta and everything after them are FP64 either way. */
+enum { SLAQ_PREC_FP32 = 0, SLAQ_PREC_FP64 = 1 };
+
 /* Size limits of this build. */
 enum { SLAQ_MAX_PROBES = 4096, SLAQ_MAX_STEPS = 64 };
 
@@ -133,6 +137,17 @@ slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int6
  * every nonzero once per tile.  0 (default) = tiles of 64 words (256 probes).
  * Changes the workspace size. */
 slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads);
+
+/* Precision of the Lanczos vectors of this graph.  Default: FP32 for the
+ * normalized Laplacian (spectrum in [0, 2]; GPU and FP64 results agree to
+ * ~1e-5 relative), FP64 for the combinatorial one, whose spectrum spans
+ * [0, 2 max D_ii]: with hubs its top eigenvalues converge within a few steps
+ * and FP32 vectors then lose orthogonality to them far sooner than FP64 ones
+ * (no reorthogonalization, as in §3.1), which moves the low Ritz values and
+ * VNGE by ~1e-4 relative.  FP64 doubles the vector traffic.  Changes the
+ * workspace size (query slaq_lanczos_workspace again). */
+slaq_status slaq_graph_set_precision(slaq_graph_t g, int precision);
+slaq_status slaq_graph_precision(slaq_graph_t g, int* precision);
 
 /* Internal storage order of the handle (waits for the build's stream).
  * relabeled: 1 if the handle relabelled its nodes; n_rows: rows of the

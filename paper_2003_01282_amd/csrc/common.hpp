@@ -91,6 +91,7 @@ struct slaq_graph_s {
     const float* weights;   // NULL = unweighted
     int laplacian;          // SLAQ_LAP_*
     float* diag;            // per internal row: dinv (normalized) or degree (combinatorial); 0 <=> no data
+    double* diag64;         // the same in FP64 (read by the FP64-vector kernels)
     const int32_t* perm;    // internal label -> caller id (NULL = identity)
     int relabeled;
     float* dinv_out;        // caller's diagonal scale, caller order
@@ -107,7 +108,8 @@ struct slaq_graph_s {
     int64_t max_heavy;       // capacity of hrow / hoff / segk (stride of the x-major arrays)
     int heavy_min;
     int piece;
-    int tile_quads;          // probe tile of the gather kernels in float4 words (0 = automatic)
+    int tile_quads;          // probe tile of the gather kernels in 16-byte words (0 = automatic)
+    int precision;           // SLAQ_PREC_* of the Lanczos vectors
     hipStream_t stream;      // stream of the build (slaq_graph_info waits on it)
 };
 
@@ -131,6 +133,7 @@ struct RelabelBuffers {
     float* w;            // [nnz]
     int32_t* tmp;        // [nnz] labels of long rows in caller order
     float* diag;         // [n]
+    double* diag64;      // [n]
     long long* len;      // [n + 1] row lengths before the scan
     long long* sort_cnt; // [kDegBuckets * chunks]
     int64_t* sort_off;   // [kDegBuckets * chunks]
@@ -139,8 +142,8 @@ struct RelabelBuffers {
 
 // Relabels the caller's CSR into B (sets st->n_rows and the range bounds).
 slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp, const int32_t* col,
-                          const float* w, const float* diag_caller, GraphStats* st, int64_t* bounds,
-                          hipStream_t stream);
+                          const float* w, const float* diag_caller, const double* diag64_caller, GraphStats* st,
+                          int64_t* bounds, hipStream_t stream);
 
 // ------------------------------------------------------- Lanczos layout ----
 // Vector blocks are row-major [n][ld], ld = nv rounded up to a multiple of 4

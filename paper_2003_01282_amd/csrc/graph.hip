@@ -34,7 +34,7 @@ enum : unsigned {
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(256) degree_kernel(int64_t n, const int64_t* __restrict__ rp,
                                                      const float* __restrict__ w, int laplacian,
-                                                     float* __restrict__ diag,
+                                                     float* __restrict__ diag, double* __restrict__ diag64,
                                                      BuildPartial* __restrict__ part) {
     double dmax = 0.0, dsum = 0.0;
     long long nz = 0;
@@ -48,12 +48,13 @@ __global__ void __launch_bounds__(256) degree_kernel(int64_t n, const int64_t* _
         } else {
             d = (double)(e - s);
         }
-        float out;
+        double out;
         if (laplacian == SLAQ_LAP_NORMALIZED)
-            out = d > 0.0 ? (float)(1.0 / sqrt(d)) : 0.0f;
+            out = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
         else
-            out = (float)d;
-        diag[i] = out;
+            out = d;
+        diag[i] = (float)out;
+        diag64[i] = out;
         dmax = fmax(dmax, d);
         dsum += d;
         nz += d > 0.0 ? 1 : 0;
@@ -400,7 +401,8 @@ slaq_status exclusive_scan(const long long* in, int64_t len, int64_t* out, long 
 
 struct ScratchLayout {
     size_t off_stats, off_part, off_counts, off_hrow, off_hoff, off_bounds, off_segk, off_cnt, off_segoff, off_bsum,
-        off_perm, off_inv, off_rp2, off_col2, off_w2, off_tmp, off_diag2, off_len, off_sortcnt, off_sortoff, total;
+        off_perm, off_inv, off_rp2, off_col2, off_w2, off_tmp, off_diag2, off_d64, off_d64r, off_len, off_sortcnt,
+        off_sortoff, total;
     int64_t nplan, max_heavy, sort_chunks;
 };
 
@@ -439,6 +441,8 @@ static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     L.off_w2 = take(sizeof(float) * (size_t)nnz);
     L.off_tmp = take(sizeof(int32_t) * (size_t)nnz);
     L.off_diag2 = take(sizeof(float) * (size_t)n);
+    L.off_d64 = take(sizeof(double) * (size_t)n);
+    L.off_d64r = take(sizeof(double) * (size_t)n);
     L.off_len = take(sizeof(long long) * ((size_t)n + 1));
     L.off_sortcnt = take(sizeof(long long) * sort_len);
     L.off_sortoff = take(sizeof(int64_t) * sort_len);
@@ -537,12 +541,13 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
                      "adjacency is not symmetric (pattern or weights)");
     }
 
+    double* d64 = (double*)(base + SL.off_d64);
     if (weights)
         hipLaunchKernelGGL(degree_kernel<true>, dim3(blocks), dim3(256), 0, st, n, row_ptr, weights,
-                           laplacian, dinv_out, part);
+                           laplacian, dinv_out, d64, part);
     else
         hipLaunchKernelGGL(degree_kernel<false>, dim3(blocks), dim3(256), 0, st, n, row_ptr, weights,
-                           laplacian, dinv_out, part);
+                           laplacian, dinv_out, d64, part);
     SLAQ_LAUNCHED();
     hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(256), 0, st, n, blocks, laplacian, part, stats);
     SLAQ_LAUNCHED();
@@ -564,6 +569,7 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->heavy_min = kDefaultHeavyMin;
     g->piece = kDefaultPiece;
     g->tile_quads = 0;
+    g->precision = laplacian == SLAQ_LAP_COMBINATORIAL ? SLAQ_PREC_FP64 : SLAQ_PREC_FP32;
     g->n = n;
     g->nnz = nnz;
     g->laplacian = laplacian;
@@ -580,11 +586,12 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
         B.w = (float*)(base + SL.off_w2);
         B.tmp = (int32_t*)(base + SL.off_tmp);
         B.diag = (float*)(base + SL.off_diag2);
+        B.diag64 = (double*)(base + SL.off_d64r);
         B.len = (long long*)(base + SL.off_len);
         B.sort_cnt = (long long*)(base + SL.off_sortcnt);
         B.sort_off = (int64_t*)(base + SL.off_sortoff);
         B.bsum = g->scanbuf;
-        const slaq_status rs = relabel_build(B, n, row_ptr, col_idx, weights, dinv_out, stats, g->bounds, st);
+        const slaq_status rs = relabel_build(B, n, row_ptr, col_idx, weights, dinv_out, d64, stats, g->bounds, st);
         if (rs != SLAQ_OK) {
             delete g;
             return rs;
@@ -593,6 +600,7 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
         g->col_idx = B.col;
         g->weights = weights ? B.w : nullptr;
         g->diag = B.diag;
+        g->diag64 = B.diag64;
         g->perm = B.perm;
         g->relabeled = 1;
     } else {
@@ -600,6 +608,7 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
         g->col_idx = col_idx;
         g->weights = weights;
         g->diag = dinv_out;
+        g->diag64 = d64;
         g->perm = nullptr;
         g->relabeled = 0;
     }
@@ -643,6 +652,22 @@ slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads) {
     SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
     SLAQ_REQUIRE(tile_quads >= 0 && tile_quads <= 64, SLAQ_ERR_INVALID_ARG, "tile_quads must be in [0, 64]");
     g->tile_quads = tile_quads;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_set_precision(slaq_graph_t g, int precision) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    SLAQ_REQUIRE(precision == SLAQ_PREC_FP32 || precision == SLAQ_PREC_FP64, SLAQ_ERR_INVALID_ARG,
+                 "unknown precision %d", precision);
+    g->precision = precision;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_precision(slaq_graph_t g, int* precision) {
+    clear_error();
+    SLAQ_REQUIRE(g && precision, SLAQ_ERR_INVALID_ARG, "graph or precision is NULL");
+    *precision = g->precision;
     return SLAQ_OK;
 }
 

@@ -14,6 +14,13 @@
 // alpha_j = q_j.w, beta_j = ||w - alpha_j q_j||) with the scalings folded into
 // the reads.  Reductions are fixed-order (no floating-point atomics).
 //
+// Vector precision V: FP32 (products of two floats are exact in FP64, so the
+// dot products are FP64 sums of exact terms) or FP64 (the whole recurrence in
+// FP64, for operators of wide spectral range such as D - A of a graph with
+// hubs, where FP32 vectors lose orthogonality to the converged top of the
+// spectrum within a few steps).  A "quad" is 16 bytes of a probe row: 4 floats
+// or 2 doubles; a lane holds one quad.
+//
 // Isolated nodes have zero rows and columns in L, so on them every R_j is a
 // multiple of the probe: R_j[i] = rho_j v[i] with rho_1 = 1, rho_0 = 0 and
 // rho_{j+1} = -tau_{j-1} rho_{j-1} - a_j rho_j.  Their rows are never stored
@@ -26,8 +33,19 @@
 
 namespace slaq {
 
-constexpr double kEpsBreakdown = 1e-6;
 constexpr int kPieceUnroll = 8;  // gathers in flight per group in the piece kernel
+
+// breakdown threshold relative to the spectral bound: above the rounding
+// noise of the vectors' precision
+template <typename V> constexpr double eps_breakdown();
+template <> constexpr double eps_breakdown<float>() { return 1e-6; }
+template <> constexpr double eps_breakdown<double>() { return 1e-10; }
+
+template <typename V>
+struct alignas(16) Quad {
+    static constexpr int E = 16 / sizeof(V);
+    V v[E];
+};
 
 // Per-probe FP64 recurrence state (workspace).
 struct ProbeState {
@@ -48,40 +66,61 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t counter) 
     return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ float4 f4(float a) { return make_float4(a, a, a, a); }
+__device__ __forceinline__ float vfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double vfma(double a, double b, double c) { return fma(a, b, c); }
 
-__device__ __forceinline__ void fma4(float s, const float4& x, float4& acc) {
-    acc.x = fmaf(s, x.x, acc.x);
-    acc.y = fmaf(s, x.y, acc.y);
-    acc.z = fmaf(s, x.z, acc.z);
-    acc.w = fmaf(s, x.w, acc.w);
+template <typename V>
+__device__ __forceinline__ Quad<V> qzero() {
+    Quad<V> q;
+#pragma unroll
+    for (int e = 0; e < Quad<V>::E; ++e) q.v[e] = V(0);
+    return q;
 }
 
-__device__ __forceinline__ void add4(float4& a, const float4& b) {
-    a.x += b.x;
-    a.y += b.y;
-    a.z += b.z;
-    a.w += b.w;
+template <typename V>
+__device__ __forceinline__ void qfma(V s, const Quad<V>& x, Quad<V>& acc) {
+#pragma unroll
+    for (int e = 0; e < Quad<V>::E; ++e) acc.v[e] = vfma(s, x.v[e], acc.v[e]);
 }
 
-__device__ __forceinline__ float4 load4(const float* p, int q) {
-    return make_float4(p[4 * q], p[4 * q + 1], p[4 * q + 2], p[4 * q + 3]);
+template <typename V>
+__device__ __forceinline__ void qadd(Quad<V>& a, const Quad<V>& b) {
+#pragma unroll
+    for (int e = 0; e < Quad<V>::E; ++e) a.v[e] += b.v[e];
 }
 
-// Fixed-order reduction of per-lane FP64 sums (4 probes per lane) over the
+// quad `q` of a per-probe coefficient vector
+template <typename V>
+__device__ __forceinline__ Quad<V> qload(const V* p, int q) {
+    Quad<V> r;
+#pragma unroll
+    for (int e = 0; e < Quad<V>::E; ++e) r.v[e] = p[Quad<V>::E * q + e];
+    return r;
+}
+
+template <typename V>
+__device__ __forceinline__ Quad<V> qshfl(const Quad<V>& a, int src) {
+    Quad<V> r;
+#pragma unroll
+    for (int e = 0; e < Quad<V>::E; ++e) r.v[e] = __shfl(a.v[e], src);
+    return r;
+}
+
+// Fixed-order reduction of per-lane FP64 sums (E probes per lane) over the
 // groups of each wave and the 4 waves of the block; writes one partial per
 // probe of this block's tile: part[p * nb + block].
-__device__ __forceinline__ void block_reduce_store(const double (&s)[4], double* __restrict__ part, int nb,
-                                                   int F, int G, int K, int ld, int tile, int TQ, int col0 = 0) {
-    __shared__ double red[4][64][4];
+template <int E>
+__device__ __forceinline__ void block_reduce_store(const double (&s)[E], double* __restrict__ part, int nb, int F,
+                                                   int G, int K, int ld, int tile, int TQ, int col0 = 0) {
+    __shared__ double red[4][64][E];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) red[wave][lane][c] = s[c];
+    for (int c = 0; c < E; ++c) red[wave][lane][c] = s[c];
     __syncthreads();
     const int t = threadIdx.x;
-    if (t < 4 * G) {
-        const int q = t >> 2, comp = t & 3;
-        const int p = tile * (4 * TQ) + t;
+    if (t < E * G) {
+        const int q = t / E, comp = t % E;
+        const int p = tile * (E * TQ) + t;
         if (tile * TQ + q < F && p < ld) {
             double a = 0.0;
             for (int wv = 0; wv < 4; ++wv)
@@ -92,10 +131,11 @@ __device__ __forceinline__ void block_reduce_store(const double (&s)[4], double*
 }
 
 // ------------------------------------------------------------- init -------
+template <typename V>
 __global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double sigma1,
                                                   double* __restrict__ alpha, double* __restrict__ beta,
                                                   int32_t* __restrict__ steps, ProbeState* __restrict__ ps,
-                                                  float* __restrict__ coef) {
+                                                  V* __restrict__ coef) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
     for (int k = t; k < nv * m; k += stride) {
@@ -111,38 +151,40 @@ __global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double 
         ps[p].rho_prev = 0.0;
         ps[p].a = 0.0;
         ps[p].active = on ? 1 : 0;
-        coef[p] = on ? (float)sigma1 : 0.0f;  // sigma_j
-        coef[ld + p] = 0.0f;                  // tau_{j-1}
-        coef[2 * ld + p] = 0.0f;              // a_j
+        coef[p] = on ? (V)sigma1 : V(0);  // sigma_j
+        coef[ld + p] = V(0);               // tau_{j-1}
+        coef[2 * ld + p] = V(0);           // a_j
     }
 }
 
 // R_1[i][p] = +-1 (bit (p mod 64) of splitmix64(seed, 64 id + p div 64), id
 // the caller's id of internal row i) on rows with data; padding probes are 0.
 // One quad per thread, rows strided.
+template <typename V>
 __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__ st, int nv, int F,
                                                   int rows_per_sweep, uint64_t seed,
-                                                  const float* __restrict__ diag,
-                                                  const int32_t* __restrict__ perm, float4* __restrict__ R) {
+                                                  const V* __restrict__ diag,
+                                                  const int32_t* __restrict__ perm, Quad<V>* __restrict__ R) {
+    constexpr int E = Quad<V>::E;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int quad = tid % F;
     const int64_t row0 = tid / F;
     if (row0 >= rows_per_sweep) return;
     const int64_t n = st->n_rows;
-    const int p0 = 4 * quad;
+    const int p0 = E * quad;
     const uint64_t word = (uint64_t)(p0 >> 6);
     const int bit0 = p0 & 63;
     for (int64_t i = row0; i < n; i += rows_per_sweep) {
-        if (diag[i] == 0.0f) continue;
+        if (diag[i] == V(0)) continue;
         const uint64_t id = perm ? (uint64_t)perm[i] : (uint64_t)i;
         const uint64_t z = splitmix64(seed, 64ull * id + word);
-        float v[4];
+        Quad<V> v;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float sgn = ((z >> (bit0 + c)) & 1ull) ? -1.0f : 1.0f;
-            v[c] = (p0 + c < nv) ? sgn : 0.0f;
+        for (int c = 0; c < E; ++c) {
+            const V sgn = ((z >> (bit0 + c)) & 1ull) ? V(-1) : V(1);
+            v.v[c] = (p0 + c < nv) ? sgn : V(0);
         }
-        R[i * F + quad] = make_float4(v[0], v[1], v[2], v[3]);
+        R[i * F + quad] = v;
     }
 }
 
@@ -150,40 +192,40 @@ __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__
 // Gather-accumulate over nonzeros [k0, k1) of one row by the group of this
 // lane: the group loads up to G column indices (and their scale) at once and
 // broadcasts them with lane shuffles; gathers are issued four at a time.
-template <int MODE, bool WEIGHTED>
-__device__ __forceinline__ void group_segment(float4& acc, int64_t k0, int64_t k1, int gbase, int gl, int G,
+template <int MODE, bool WEIGHTED, typename V>
+__device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t k1, int gbase, int gl, int G,
                                               const int32_t* __restrict__ col, const float* __restrict__ w,
-                                              const float* __restrict__ diag, const float4* __restrict__ R,
+                                              const V* __restrict__ diag, const Quad<V>* __restrict__ R,
                                               int F, int quad, bool lane_ok) {
     for (int64_t kb = k0; kb < k1; kb += G) {
         const int cnt = (int)((k1 - kb) < G ? (k1 - kb) : G);
         int32_t cl = 0;
-        float sl = 0.0f;
+        V sl = V(0);
         if (gl < cnt) {
             cl = col[kb + gl];
-            float sc = WEIGHTED ? w[kb + gl] : 1.0f;
+            V sc = WEIGHTED ? (V)w[kb + gl] : V(1);
             if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[cl];
             sl = sc;
         }
         int u = 0;
         for (; u + 4 <= cnt; u += 4) {
             int32_t c[4];
-            float s[4];
-            float4 x[4];
+            V s[4];
+            Quad<V> x[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 c[v] = __shfl(cl, gbase + u + v);
                 s[v] = __shfl(sl, gbase + u + v);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? R[(int64_t)c[v] * F + quad] : f4(0.0f);
+            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? R[(int64_t)c[v] * F + quad] : qzero<V>();
 #pragma unroll
-            for (int v = 0; v < 4; ++v) fma4(s[v], x[v], acc);
+            for (int v = 0; v < 4; ++v) qfma(s[v], x[v], acc);
         }
         for (; u < cnt; ++u) {
             const int32_t c = __shfl(cl, gbase + u);
-            const float s = __shfl(sl, gbase + u);
-            if (lane_ok) fma4(s, R[(int64_t)c * F + quad], acc);
+            const V s = __shfl(sl, gbase + u);
+            if (lane_ok) qfma(s, R[(int64_t)c * F + quad], acc);
         }
     }
 }
@@ -193,15 +235,15 @@ __device__ __forceinline__ void group_segment(float4& acc, int64_t k0, int64_t k
 // blockIdx.x % 8 == x, which the dispatcher places on one XCD; each wave walks
 // a contiguous run of its range's pieces so the owning heavy row advances
 // incrementally.
-template <int MODE, bool WEIGHTED>
+template <int MODE, bool WEIGHTED, typename V>
 __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict__ st,
                                                    const int64_t* __restrict__ segk,
                                                    const int64_t* __restrict__ segoff, int64_t cap,
                                                    const int32_t* __restrict__ col,
                                                    const float* __restrict__ w,
-                                                   const float* __restrict__ diag,
-                                                   const float4* __restrict__ R,
-                                                   float4* __restrict__ P, int F, int G, int K, int piece,
+                                                   const V* __restrict__ diag,
+                                                   const Quad<V>* __restrict__ R,
+                                                   Quad<V>* __restrict__ P, int F, int G, int K, int piece,
                                                    int tile0, int TQ) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
@@ -235,15 +277,15 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
         const int64_t kend = segk[(int64_t)(x + 1) * cap + h];
         const int64_t k0 = kstart + (p - so[h]) * piece;
         const int64_t k1 = k0 + piece < kend ? k0 + piece : kend;
-        float4 acc = f4(0.0f);
+        Quad<V> acc = qzero<V>();
         // the wave loads 64 column indices at a time; group gi takes u = gi, gi+K, ...
         for (int64_t kb = k0; kb < k1; kb += 64) {
             const int cnt = (int)((k1 - kb) < 64 ? (k1 - kb) : 64);
             int32_t cl = 0;
-            float sl = 0.0f;
+            V sl = V(0);
             if (lane < cnt) {
                 cl = col[kb + lane];
-                float sc = WEIGHTED ? w[kb + lane] : 1.0f;
+                V sc = WEIGHTED ? (V)w[kb + lane] : V(1);
                 if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[cl];
                 sl = sc;
             }
@@ -251,93 +293,81 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
             int r = 0;
             for (; r + kPieceUnroll <= rounds; r += kPieceUnroll) {
                 int32_t c[kPieceUnroll];
-                float s[kPieceUnroll];
-                float4 x[kPieceUnroll];
+                V s[kPieceUnroll];
+                Quad<V> xv[kPieceUnroll];
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v) {
                     const int u = (r + v) * K + gi;
                     const int src = u < 64 ? u : 63;
                     c[v] = __shfl(cl, src);
                     s[v] = __shfl(sl, src);
-                    if (!(in_group && u < cnt)) s[v] = 0.0f;
+                    if (!(in_group && u < cnt)) s[v] = V(0);
                 }
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v)
-                    x[v] = (lane_ok && s[v] != 0.0f) ? R[(int64_t)c[v] * F + quad] : f4(0.0f);
+                    xv[v] = (lane_ok && s[v] != V(0)) ? R[(int64_t)c[v] * F + quad] : qzero<V>();
 #pragma unroll
-                for (int v = 0; v < kPieceUnroll; ++v) fma4(s[v], x[v], acc);
+                for (int v = 0; v < kPieceUnroll; ++v) qfma(s[v], xv[v], acc);
             }
             for (; r < rounds; ++r) {
                 const int u = r * K + gi;
                 const int src = u < 64 ? u : 63;
                 const int32_t c = __shfl(cl, src);
-                const float s = __shfl(sl, src);
-                if (lane_ok && u < cnt) fma4(s, R[(int64_t)c * F + quad], acc);
+                const V s = __shfl(sl, src);
+                if (lane_ok && u < cnt) qfma(s, R[(int64_t)c * F + quad], acc);
             }
         }
         // fixed-order tree over the K groups (lane + st*G)
         for (int sd = 1; sd < K; sd <<= 1) {
             const int src = lane + sd * G < 64 ? lane + sd * G : lane;
-            float4 o;
-            o.x = __shfl(acc.x, src);
-            o.y = __shfl(acc.y, src);
-            o.z = __shfl(acc.z, src);
-            o.w = __shfl(acc.w, src);
-            if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) add4(acc, o);
+            const Quad<V> o = qshfl(acc, src);
+            if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) qadd(acc, o);
         }
         if (gi == 0 && quad < F) P[p * F + quad] = acc;
     }
 }
 
 // Row epilogue shared by the row and heavy-row kernels: w_i = sigma (L R_j)_i
-// - tau R_{j-1}[i], stored; returns the FP64 products R_j[i] * w_i in s1.
-template <int MODE>
-__device__ __forceinline__ void row_epilogue(int64_t i, const float4& acc, const float* __restrict__ diag,
-                                             const float4* __restrict__ R, const float4* __restrict__ Rp,
-                                             float4* __restrict__ W, const float4& sg, const float4& tp,
-                                             int has_prev, int F, int quad, double (&s1)[4]) {
-    const float4 ri = R[i * F + quad];
-    const float di = diag[i];
-    float4 lr;  // (L R_j)_i
-    if (MODE == SLAQ_LAP_NORMALIZED) {
-        lr.x = fmaf(-di, acc.x, ri.x);
-        lr.y = fmaf(-di, acc.y, ri.y);
-        lr.z = fmaf(-di, acc.z, ri.z);
-        lr.w = fmaf(-di, acc.w, ri.w);
-    } else {
-        lr.x = fmaf(di, ri.x, -acc.x);
-        lr.y = fmaf(di, ri.y, -acc.y);
-        lr.z = fmaf(di, ri.z, -acc.z);
-        lr.w = fmaf(di, ri.w, -acc.w);
+// - tau R_{j-1}[i], stored; accumulates the FP64 products R_j[i] * w_i in s1.
+template <int MODE, typename V>
+__device__ __forceinline__ void row_epilogue(int64_t i, const Quad<V>& acc, const V* __restrict__ diag,
+                                             const Quad<V>* __restrict__ R, const Quad<V>* __restrict__ Rp,
+                                             Quad<V>* __restrict__ W, const Quad<V>& sg, const Quad<V>& tp,
+                                             int has_prev, int F, int quad, double (&s1)[Quad<V>::E]) {
+    constexpr int E = Quad<V>::E;
+    const Quad<V> ri = R[i * F + quad];
+    const V di = diag[i];
+    Quad<V> wi;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        // (L R_j)_i
+        const V lr = MODE == SLAQ_LAP_NORMALIZED ? vfma(-di, acc.v[e], ri.v[e]) : vfma(di, ri.v[e], -acc.v[e]);
+        wi.v[e] = sg.v[e] * lr;
     }
-    float4 wi = make_float4(sg.x * lr.x, sg.y * lr.y, sg.z * lr.z, sg.w * lr.w);
     if (has_prev) {
-        const float4 rq = Rp[i * F + quad];
-        wi.x = fmaf(-tp.x, rq.x, wi.x);
-        wi.y = fmaf(-tp.y, rq.y, wi.y);
-        wi.z = fmaf(-tp.z, rq.z, wi.z);
-        wi.w = fmaf(-tp.w, rq.w, wi.w);
+        const Quad<V> rq = Rp[i * F + quad];
+#pragma unroll
+        for (int e = 0; e < E; ++e) wi.v[e] = vfma(-tp.v[e], rq.v[e], wi.v[e]);
     }
     W[i * F + quad] = wi;
-    // products of two floats are exact in double
-    s1[0] = fma((double)ri.x, (double)wi.x, s1[0]);
-    s1[1] = fma((double)ri.y, (double)wi.y, s1[1]);
-    s1[2] = fma((double)ri.z, (double)wi.z, s1[2]);
-    s1[3] = fma((double)ri.w, (double)wi.w, s1[3]);
+    // FP32: products of two floats are exact in double
+#pragma unroll
+    for (int e = 0; e < E; ++e) s1[e] = fma((double)ri.v[e], (double)wi.v[e], s1[e]);
 }
 
 // Heavy rows: one wave per row sums the row's pieces (all column ranges, the
 // K groups taking every K-th piece, then a fixed-order tree), then the row
 // epilogue.  Dot partials go to columns col0 + block of `part`.
-template <int MODE>
+template <int MODE, typename V>
 __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__ st,
                                                   const int32_t* __restrict__ hrow,
                                                   const int64_t* __restrict__ segoff, int64_t cap,
-                                                  const float4* __restrict__ P, const float* __restrict__ diag,
-                                                  const float4* __restrict__ R, const float4* __restrict__ Rp,
-                                                  float4* __restrict__ W, const float* __restrict__ coef,
+                                                  const Quad<V>* __restrict__ P, const V* __restrict__ diag,
+                                                  const Quad<V>* __restrict__ R, const Quad<V>* __restrict__ Rp,
+                                                  Quad<V>* __restrict__ W, const V* __restrict__ coef,
                                                   int has_prev, double* __restrict__ part, int nb, int col0, int F,
                                                   int G, int K, int ld, int tile0, int TQ) {
+    constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int tile = tile0 + (int)blockIdx.y;
@@ -345,58 +375,58 @@ __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
     const int64_t nh = st->n_heavy;
-    double s1[4] = {0.0, 0.0, 0.0, 0.0};
-    float4 sg = f4(0.0f), tp = f4(0.0f);
+    double s1[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) s1[e] = 0.0;
+    Quad<V> sg = qzero<V>(), tp = qzero<V>();
     if (lane_ok) {
-        sg = load4(coef, quad);
-        if (has_prev) tp = load4(coef + ld, quad);
+        sg = qload(coef, quad);
+        if (has_prev) tp = qload(coef + ld, quad);
     }
     for (int64_t h = (int64_t)blockIdx.x * 4 + wave; h < nh; h += (int64_t)gridDim.x * 4) {
-        float4 acc = f4(0.0f);
+        Quad<V> acc = qzero<V>();
         int64_t idx = 0;  // position in the row's piece list (ranges in order)
         for (int x = 0; x < kColRanges; ++x) {
             const int64_t p0 = segoff[(int64_t)x * cap + h], p1 = segoff[(int64_t)x * cap + h + 1];
             // first piece of this range owned by group gi
             int64_t p = p0 + ((gi - idx) % K + K) % K;
             for (; p + 3 * K < p1; p += 4 * K) {
-                float4 xv[4];
+                Quad<V> xv[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) xv[v] = lane_ok ? P[(p + v * K) * F + quad] : f4(0.0f);
+                for (int v = 0; v < 4; ++v) xv[v] = lane_ok ? P[(p + v * K) * F + quad] : qzero<V>();
 #pragma unroll
-                for (int v = 0; v < 4; ++v) add4(acc, xv[v]);
+                for (int v = 0; v < 4; ++v) qadd(acc, xv[v]);
             }
             for (; p < p1; p += K)
-                if (lane_ok) add4(acc, P[p * F + quad]);
+                if (lane_ok) qadd(acc, P[p * F + quad]);
             idx += p1 - p0;
         }
         for (int sd = 1; sd < K; sd <<= 1) {
             const int src = lane + sd * G < 64 ? lane + sd * G : lane;
-            float4 o;
-            o.x = __shfl(acc.x, src);
-            o.y = __shfl(acc.y, src);
-            o.z = __shfl(acc.z, src);
-            o.w = __shfl(acc.w, src);
-            if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) add4(acc, o);
+            const Quad<V> o = qshfl(acc, src);
+            if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) qadd(acc, o);
         }
-        if (gi == 0 && lane_ok) row_epilogue<MODE>((int64_t)hrow[h], acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
+        if (gi == 0 && lane_ok)
+            row_epilogue<MODE, V>((int64_t)hrow[h], acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
     }
-    block_reduce_store(s1, part, nb, F, G, K, ld, tile, TQ, col0);
+    block_reduce_store<E>(s1, part, nb, F, G, K, ld, tile, TQ, col0);
 }
 
-// Every non-isolated row: w = sigma (L R_j)_i - tau R_{j-1}[i]; partial R_j.w.
-// A wave takes windows of 64 rows (row offsets loaded by its lanes at once);
-// group gi handles rows gi, gi+K, ... of the window.
-template <int MODE, bool WEIGHTED>
+// Every light row with data: w = sigma (L R_j)_i - tau R_{j-1}[i]; partial
+// R_j.w.  A wave takes windows of rw rows (row offsets loaded by its lanes at
+// once); group gi handles rows gi, gi+K, ... of the window.
+template <int MODE, bool WEIGHTED, typename V>
 __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ st, const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ w,
-                                                 const float* __restrict__ diag,
+                                                 const V* __restrict__ diag,
                                                  int heavy_min,
-                                                 const float4* __restrict__ R,
-                                                 const float4* __restrict__ Rp,
-                                                 float4* __restrict__ W, const float* __restrict__ coef,
+                                                 const Quad<V>* __restrict__ R,
+                                                 const Quad<V>* __restrict__ Rp,
+                                                 Quad<V>* __restrict__ W, const V* __restrict__ coef,
                                                  int has_prev, double* __restrict__ part, int nb, int F, int G,
                                                  int K, int ld, int rw, int tile0, int TQ) {
+    constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int gbase = gi * G;
@@ -405,11 +435,13 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
 
-    double s1[4] = {0.0, 0.0, 0.0, 0.0};
-    float4 sg = f4(0.0f), tp = f4(0.0f);
+    double s1[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) s1[e] = 0.0;
+    Quad<V> sg = qzero<V>(), tp = qzero<V>();
     if (lane_ok) {
-        sg = load4(coef, quad);
-        if (has_prev) tp = load4(coef + ld, quad);
+        sg = qload(coef, quad);
+        if (has_prev) tp = qload(coef + ld, quad);
     }
     const int64_t n = st->n_rows;
     const int rounds = (rw + K - 1) / K;
@@ -427,58 +459,58 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
             const int64_t i = r0 + t;
             if (!in_group || t >= rw || i >= n || e == s) continue;  // isolated: nothing stored
             if (e - s >= heavy_min) continue;  // heavy rows: spmm_heavy
-            float4 acc = f4(0.0f);
-            group_segment<MODE, WEIGHTED>(acc, s, e, gbase, gl, G, col, w, diag, R, F, quad, lane_ok);
+            Quad<V> acc = qzero<V>();
+            group_segment<MODE, WEIGHTED, V>(acc, s, e, gbase, gl, G, col, w, diag, R, F, quad, lane_ok);
             if (!lane_ok) continue;
-            row_epilogue<MODE>(i, acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
+            row_epilogue<MODE, V>(i, acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
         }
     }
-    block_reduce_store(s1, part, nb, F, G, K, ld, tile, TQ);
+    block_reduce_store<E>(s1, part, nb, F, G, K, ld, tile, TQ);
 }
 
-// R_{j+1} = w - a_j R_j on non-isolated rows (stored when `store`), partial
+// R_{j+1} = w - a_j R_j on rows with data (stored when `store`), partial
 // sums of ||R_{j+1}||^2.  Same wave/group layout as spmm_rows.
-__global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st, const float* __restrict__ diag,
-                                              const float4* __restrict__ W, const float4* __restrict__ R,
-                                              const float* __restrict__ coef, int store,
-                                              float4* __restrict__ Rn, double* __restrict__ part, int nb,
+template <typename V>
+__global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st, const V* __restrict__ diag,
+                                              const Quad<V>* __restrict__ W, const Quad<V>* __restrict__ R,
+                                              const V* __restrict__ coef, int store,
+                                              Quad<V>* __restrict__ Rn, double* __restrict__ part, int nb,
                                               int F, int G, int K, int ld, int rw, int tile0, int TQ) {
+    constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int tile = tile0 + (int)blockIdx.y;
     const int quad = tile * TQ + gl;
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
-    double s2[4] = {0.0, 0.0, 0.0, 0.0};
-    float4 a = f4(0.0f);
-    if (lane_ok) a = load4(coef + 2 * ld, quad);
+    double s2[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) s2[e] = 0.0;
+    Quad<V> a = qzero<V>();
+    if (lane_ok) a = qload(coef + 2 * ld, quad);
     const int64_t n = st->n_rows;
     const int rounds = (rw + K - 1) / K;
     const int64_t nwin = (n + rw - 1) / rw;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += nwaves) {
         const int64_t r0 = win * rw;
-        const float d_l = r0 + lane < n ? diag[r0 + lane] : 0.0f;
+        const V d_l = r0 + lane < n ? diag[r0 + lane] : V(0);
         for (int rr = 0; rr < rounds; ++rr) {
             const int t = rr * K + gi;
-            const float d = __shfl(d_l, t < 64 ? t : 63);
+            const V d = __shfl(d_l, t < 64 ? t : 63);
             const int64_t i = r0 + t;
-            if (!lane_ok || t >= rw || i >= n || d == 0.0f) continue;
-            const float4 wv = W[i * F + quad];
-            const float4 rv = R[i * F + quad];
-            float4 r;
-            r.x = fmaf(-a.x, rv.x, wv.x);
-            r.y = fmaf(-a.y, rv.y, wv.y);
-            r.z = fmaf(-a.z, rv.z, wv.z);
-            r.w = fmaf(-a.w, rv.w, wv.w);
+            if (!lane_ok || t >= rw || i >= n || d == V(0)) continue;
+            const Quad<V> wv = W[i * F + quad];
+            const Quad<V> rv = R[i * F + quad];
+            Quad<V> r;
+#pragma unroll
+            for (int e = 0; e < E; ++e) r.v[e] = vfma(-a.v[e], rv.v[e], wv.v[e]);
             if (store) Rn[i * F + quad] = r;
-            s2[0] = fma((double)r.x, (double)r.x, s2[0]);
-            s2[1] = fma((double)r.y, (double)r.y, s2[1]);
-            s2[2] = fma((double)r.z, (double)r.z, s2[2]);
-            s2[3] = fma((double)r.w, (double)r.w, s2[3]);
+#pragma unroll
+            for (int e = 0; e < E; ++e) s2[e] = fma((double)r.v[e], (double)r.v[e], s2[e]);
         }
     }
-    block_reduce_store(s2, part, nb, F, G, K, ld, tile, TQ);
+    block_reduce_store<E>(s2, part, nb, F, G, K, ld, tile, TQ);
 }
 
 // ---------------------------------------------------------- finalize ------
@@ -496,15 +528,16 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return red[0];
 }
 
+template <typename V>
 __global__ void __launch_bounds__(256) finalize_a(const double* __restrict__ part, int nb, int ld, int m, int j,
                                                   const GraphStats* __restrict__ st, ProbeState* __restrict__ ps,
-                                                  double* __restrict__ alpha, float* __restrict__ coef) {
+                                                  double* __restrict__ alpha, V* __restrict__ coef) {
     const int p = blockIdx.x;
     const double s1 = sum_partials(part, nb, p);
     if (threadIdx.x != 0) return;
     ProbeState s = ps[p];
     if (!s.active) {
-        coef[2 * ld + p] = 0.0f;
+        coef[2 * ld + p] = V(0);
         return;
     }
     // isolated rows: R_j[i] = rho_j v_i, w_i = -tau_{j-1} rho_{j-1} v_i
@@ -513,13 +546,14 @@ __global__ void __launch_bounds__(256) finalize_a(const double* __restrict__ par
     alpha[(int64_t)p * m + (j - 1)] = al;
     s.a = al * s.sigma;
     ps[p].a = s.a;
-    coef[2 * ld + p] = (float)s.a;
+    coef[2 * ld + p] = (V)s.a;
 }
 
+template <typename V>
 __global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ part, int nb, int ld, int m, int j,
                                                   const GraphStats* __restrict__ st, int laplacian, double eps_bd,
                                                   ProbeState* __restrict__ ps, double* __restrict__ beta,
-                                                  int32_t* __restrict__ steps, float* __restrict__ coef) {
+                                                  int32_t* __restrict__ steps, V* __restrict__ coef) {
     const int p = blockIdx.x;
     const double s2 = sum_partials(part, nb, p);
     if (threadIdx.x != 0) return;
@@ -535,16 +569,16 @@ __global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ par
         s.active = 0;
         s.sigma = 0.0;
         s.tau = 0.0;
-        coef[p] = 0.0f;
-        coef[ld + p] = 0.0f;
-        coef[2 * ld + p] = 0.0f;
+        coef[p] = V(0);
+        coef[ld + p] = V(0);
+        coef[2 * ld + p] = V(0);
     } else {
         s.tau = be * s.sigma;
         s.sigma = 1.0 / be;
         s.rho_prev = s.rho;
         s.rho = rho_next;
-        coef[p] = (float)s.sigma;
-        coef[ld + p] = (float)s.tau;
+        coef[p] = (V)s.sigma;
+        coef[ld + p] = (V)s.tau;
     }
     ps[p] = s;
 }
@@ -570,10 +604,12 @@ static int resident_blocks(K kernel, int block) {
     return cus * per_cu;
 }
 
+template <typename V>
 static Layout make_layout(const slaq_graph_s* g, int nv) {
+    constexpr int E = Quad<V>::E;
     Layout L{};
     L.ld = lanczos_ld(nv);
-    L.F = L.ld / 4;
+    L.F = L.ld / E;
     // probe tiles of the gather kernels, run one after another (a tile's
     // gathered rows are narrower and stay in cache longer, but every nonzero
     // is visited once per tile; on R-MAT scale 22 with nv = 100 one tile is
@@ -598,8 +634,8 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     const int64_t nwin = (g->n + L.rw - 1) / L.rw;
     int64_t nb = (nwin + 3) / 4;
     if (nb < 1) nb = 1;
-    static const int rows_cap = resident_blocks(spmm_rows<SLAQ_LAP_NORMALIZED, false>, kSpmmBlock);
-    static const int upd_cap = resident_blocks(update, kSpmmBlock);
+    static const int rows_cap = resident_blocks(spmm_rows<SLAQ_LAP_NORMALIZED, false, V>, kSpmmBlock);
+    static const int upd_cap = resident_blocks(update<V>, kSpmmBlock);
     const int cap_r = rows_cap < kRowBlocks ? rows_cap : kRowBlocks;
     const int cap_u = upd_cap < kRowBlocks ? upd_cap : kRowBlocks;
     L.nb_rows = (int)(nb < cap_r ? nb : cap_r);
@@ -611,14 +647,14 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     int64_t pb = (L.max_pieces + 3) / 4;
     pb = pb < kPieceBlocks ? (pb > 0 ? pb : 1) : kPieceBlocks;
     L.piece_blocks = (int)((pb + kColRanges - 1) / kColRanges * kColRanges);  // a multiple of the ranges
-    const size_t vec = align_up((size_t)g->n * L.ld * sizeof(float), 256);
+    const size_t vec = align_up((size_t)g->n * L.ld * sizeof(V), 256);
     size_t off = 0;
     for (int b = 0; b < 3; ++b) {
         L.off_r[b] = off;
         off += vec;
     }
     L.off_p = off;
-    off += align_up((size_t)L.max_pieces * L.ld * sizeof(float), 256);
+    off += align_up((size_t)L.max_pieces * L.ld * sizeof(V), 256);
     // heavy-row epilogue grid: one wave per heavy row, at most 1024 blocks
     {
         int64_t hb = (heavy_cap + 3) / 4;
@@ -631,7 +667,7 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     L.off_ps = off;
     off += align_up((size_t)L.ld * sizeof(ProbeState), 256);
     L.off_coef = off;
-    off += align_up((size_t)3 * L.ld * sizeof(float), 256);
+    off += align_up((size_t)3 * L.ld * sizeof(V), 256);
     L.total = off;
     return L;
 }
@@ -645,63 +681,46 @@ static int sweep_grid(int64_t n, int F, int* rows_per_sweep) {
     return (int)(((int64_t)F * rows + 255) / 256);
 }
 
-}  // namespace slaq
-
-using namespace slaq;
-
-#define SLAQ_DISPATCH(MODE_, WEIGHTED_, KERNEL, ...)                                               \
-    do {                                                                                            \
-        if ((MODE_) == SLAQ_LAP_NORMALIZED) {                                                       \
-            if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, true>), __VA_ARGS__);    \
-            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, false>), __VA_ARGS__);             \
-        } else {                                                                                    \
-            if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, true>), __VA_ARGS__); \
-            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, false>), __VA_ARGS__);          \
-        }                                                                                           \
+#define SLAQ_DISPATCH(MODE_, WEIGHTED_, KERNEL, ...)                                                  \
+    do {                                                                                               \
+        if ((MODE_) == SLAQ_LAP_NORMALIZED) {                                                          \
+            if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, true, V>), __VA_ARGS__);    \
+            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, false, V>), __VA_ARGS__);             \
+        } else {                                                                                       \
+            if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, true, V>), __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, false, V>), __VA_ARGS__);          \
+        }                                                                                              \
     } while (0)
 
-extern "C" {
+// diagonal scale of the internal rows in the vectors' precision
+template <typename V> static const V* diag_of(const slaq_graph_s* g);
+template <> const float* diag_of<float>(const slaq_graph_s* g) { return g->diag; }
+template <> const double* diag_of<double>(const slaq_graph_s* g) { return g->diag64; }
 
-slaq_status slaq_lanczos_workspace(slaq_graph_t g, int nv, int m, size_t* bytes) {
-    clear_error();
-    SLAQ_REQUIRE(g && bytes, SLAQ_ERR_INVALID_ARG, "graph or bytes is NULL");
-    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
-                 SLAQ_MAX_PROBES);
-    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
-    *bytes = make_layout(g, nv).total;
-    return SLAQ_OK;
-}
-
-slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha, double* beta,
-                         int32_t* steps, void* workspace, size_t workspace_bytes, void* stream) {
-    clear_error();
-    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
-    SLAQ_REQUIRE(alpha && beta && steps && workspace, SLAQ_ERR_INVALID_ARG,
-                 "alpha, beta, steps and workspace must be non-NULL");
-    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
-                 SLAQ_MAX_PROBES);
-    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
-    SLAQ_REQUIRE(((uintptr_t)workspace & 255) == 0, SLAQ_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(g, nv);
+template <typename V>
+static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha, double* beta,
+                               int32_t* steps, void* workspace, size_t workspace_bytes, hipStream_t st) {
+    using Q = Quad<V>;
+    const Layout L = make_layout<V>(g, nv);
     SLAQ_REQUIRE(workspace_bytes >= L.total, SLAQ_ERR_WORKSPACE, "lanczos workspace needs %zu bytes, got %zu",
                  L.total, workspace_bytes);
-    hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
-    float4* Rb[3] = {(float4*)(ws + L.off_r[0]), (float4*)(ws + L.off_r[1]), (float4*)(ws + L.off_r[2])};
-    float4* P = (float4*)(ws + L.off_p);
+    Q* Rb[3] = {(Q*)(ws + L.off_r[0]), (Q*)(ws + L.off_r[1]), (Q*)(ws + L.off_r[2])};
+    Q* P = (Q*)(ws + L.off_p);
     double* part1 = (double*)(ws + L.off_part1);
     double* part2 = (double*)(ws + L.off_part2);
     ProbeState* ps = (ProbeState*)(ws + L.off_ps);
-    float* coef = (float*)(ws + L.off_coef);
+    V* coef = (V*)(ws + L.off_coef);
     const int mode = g->laplacian;
     const bool weighted = g->weights != nullptr;
+    const V* diag = diag_of<V>(g);
 
     const double sigma1 = 1.0 / sqrt((double)g->n);
-    hipLaunchKernelGGL(state_init, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef);
+    hipLaunchKernelGGL(state_init<V>, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef);
     SLAQ_LAUNCHED();
     int rps = 0;
     const int sgrid = sweep_grid(g->n, L.F, &rps);
-    hipLaunchKernelGGL(probe_init, dim3(sgrid), dim3(256), 0, st, g->stats, nv, L.F, rps, seed, g->diag, g->perm,
+    hipLaunchKernelGGL(probe_init<V>, dim3(sgrid), dim3(256), 0, st, g->stats, nv, L.F, rps, seed, diag, g->perm,
                        Rb[0]);
     SLAQ_LAUNCHED();
 
@@ -715,41 +734,41 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
             if (L.max_pieces > 0) {
                 SLAQ_TIMED("spmm_pieces", st,
                            SLAQ_DISPATCH(mode, weighted, spmm_pieces, dim3(L.piece_blocks, 1), dim3(256), 0, st,
-                                         g->stats, g->segk, g->segoff, cap, g->col_idx, g->weights, g->diag, Rb[cur], P,
+                                         g->stats, g->segk, g->segoff, cap, g->col_idx, g->weights, diag, Rb[cur], P,
                                          L.F, L.G, L.K, g->piece, tile, L.TQ));
                 SLAQ_LAUNCHED();
             }
             SLAQ_TIMED("spmm_rows", st,
                        SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st, g->stats,
-                                     g->row_ptr, g->col_idx, g->weights, g->diag, g->heavy_min, Rb[cur], Rb[prev],
+                                     g->row_ptr, g->col_idx, g->weights, diag, g->heavy_min, Rb[cur], Rb[prev],
                                      Rb[wbuf], coef, hp, part1, nbp, L.F, L.G, L.K, L.ld, L.rw, tile, L.TQ));
             SLAQ_LAUNCHED();
             {  // always launched: its blocks write their (zero) dot partials even without heavy rows
                 SLAQ_TIMED("spmm_heavy", st, {
                     if (mode == SLAQ_LAP_NORMALIZED)
-                        hipLaunchKernelGGL(spmm_heavy<SLAQ_LAP_NORMALIZED>, dim3(L.nb_heavy, 1), dim3(256), 0, st,
-                                           g->stats, g->hrow, g->segoff, cap, P, g->diag, Rb[cur], Rb[prev], Rb[wbuf],
-                                           coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
+                        hipLaunchKernelGGL((spmm_heavy<SLAQ_LAP_NORMALIZED, V>), dim3(L.nb_heavy, 1), dim3(256), 0,
+                                           st, g->stats, g->hrow, g->segoff, cap, P, diag, Rb[cur], Rb[prev],
+                                           Rb[wbuf], coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
                     else
-                        hipLaunchKernelGGL(spmm_heavy<SLAQ_LAP_COMBINATORIAL>, dim3(L.nb_heavy, 1), dim3(256), 0, st,
-                                           g->stats, g->hrow, g->segoff, cap, P, g->diag, Rb[cur], Rb[prev], Rb[wbuf],
-                                           coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
+                        hipLaunchKernelGGL((spmm_heavy<SLAQ_LAP_COMBINATORIAL, V>), dim3(L.nb_heavy, 1), dim3(256), 0,
+                                           st, g->stats, g->hrow, g->segoff, cap, P, diag, Rb[cur], Rb[prev],
+                                           Rb[wbuf], coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
                 });
                 SLAQ_LAUNCHED();
             }
         }
         SLAQ_TIMED("finalize", st,
-                   hipLaunchKernelGGL(finalize_a, dim3(nv), dim3(256), 0, st, part1, nbp, L.ld, m, j,
+                   hipLaunchKernelGGL(finalize_a<V>, dim3(nv), dim3(256), 0, st, part1, nbp, L.ld, m, j,
                                       g->stats, ps, alpha, coef));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("update", st,
-                   hipLaunchKernelGGL(update, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->stats, g->diag,
-                                      Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F, L.Gu,
-                                      L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
+                   hipLaunchKernelGGL(update<V>, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->stats,
+                                      diag, Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F,
+                                      L.Gu, L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
-                   hipLaunchKernelGGL(finalize_b, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,
-                                      g->stats, mode, kEpsBreakdown, ps, beta, steps, coef));
+                   hipLaunchKernelGGL(finalize_b<V>, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,
+                                      g->stats, mode, eps_breakdown<V>(), ps, beta, steps, coef));
         SLAQ_LAUNCHED();
         if (j < m) {
             const int t = cur;
@@ -758,6 +777,38 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
         }
     }
     return SLAQ_OK;
+}
+
+}  // namespace slaq
+
+using namespace slaq;
+
+extern "C" {
+
+slaq_status slaq_lanczos_workspace(slaq_graph_t g, int nv, int m, size_t* bytes) {
+    clear_error();
+    SLAQ_REQUIRE(g && bytes, SLAQ_ERR_INVALID_ARG, "graph or bytes is NULL");
+    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
+                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
+    *bytes = g->precision == SLAQ_PREC_FP64 ? make_layout<double>(g, nv).total : make_layout<float>(g, nv).total;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha, double* beta,
+                         int32_t* steps, void* workspace, size_t workspace_bytes, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    SLAQ_REQUIRE(alpha && beta && steps && workspace, SLAQ_ERR_INVALID_ARG,
+                 "alpha, beta, steps and workspace must be non-NULL");
+    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
+                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
+    SLAQ_REQUIRE(((uintptr_t)workspace & 255) == 0, SLAQ_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    if (g->precision == SLAQ_PREC_FP64)
+        return run_lanczos<double>(g, nv, m, seed, alpha, beta, steps, workspace, workspace_bytes, st);
+    return run_lanczos<float>(g, nv, m, seed, alpha, beta, steps, workspace, workspace_bytes, st);
 }
 
 }  // extern "C"

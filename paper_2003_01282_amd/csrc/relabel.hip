@@ -20,7 +20,7 @@
 //   sort_scatter   stable ranks within (key, chunk) by wave ballots; rank r
 //                  of the n_act non-isolated nodes gets label
 //                  base(r mod 8) + r div 8, isolated nodes labels >= n_act
-//   relabel_len    row lengths and diagonal scale in label order
+//   relabel_len    row lengths and diagonal scale (FP32 and FP64) in label order
 //   scan           row offsets of the relabelled CSR
 //   range bounds   base(x), x = 0..8
 //   relabel_rows   one wave per row: columns mapped to labels (one gather
@@ -103,19 +103,25 @@ __global__ void __launch_bounds__(64) sort_scatter(int64_t n, const int64_t* __r
 // Row lengths (len[n] = 0 closes the scan) and the diagonal scale by label.
 __global__ void __launch_bounds__(256) relabel_len(int64_t n, const GraphStats* __restrict__ st,
                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ perm,
-                                                   const float* __restrict__ diag_caller, long long* __restrict__ len,
-                                                   float* __restrict__ diag2) {
+                                                   const float* __restrict__ diag_caller,
+                                                   const double* __restrict__ diag64_caller, long long* __restrict__ len,
+                                                   float* __restrict__ diag2, double* __restrict__ diag64) {
     const int64_t nr = st->n_rows;
     for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L <= n; L += (int64_t)gridDim.x * 256) {
         long long d = 0;
         float dg = 0.0f;
+        double dg64 = 0.0;
         if (L < nr) {
             const int64_t o = perm[L];
             d = rp[o + 1] - rp[o];
             dg = diag_caller[o];
+            dg64 = diag64_caller[o];
         }
         len[L] = d;
-        if (L < n) diag2[L] = dg;
+        if (L < n) {
+            diag2[L] = dg;
+            diag64[L] = dg64;
+        }
     }
 }
 
@@ -220,8 +226,8 @@ __global__ void __launch_bounds__(256) relabel_rows(const GraphStats* __restrict
 }
 
 slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp, const int32_t* col,
-                          const float* w, const float* diag_caller, GraphStats* st, int64_t* bounds,
-                          hipStream_t stream) {
+                          const float* w, const float* diag_caller, const double* diag64_caller, GraphStats* st,
+                          int64_t* bounds, hipStream_t stream) {
     const int64_t nblk = (n + kSortChunk - 1) / kSortChunk;
     hipLaunchKernelGGL(sort_count, dim3((unsigned)nblk), dim3(256), 0, stream, n, rp, nblk, B.sort_cnt);
     SLAQ_LAUNCHED();
@@ -233,7 +239,8 @@ slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp,
     SLAQ_LAUNCHED();
     int lb = (int)((n + 1 + 255) / 256);
     if (lb > 4096) lb = 4096;
-    hipLaunchKernelGGL(relabel_len, dim3(lb), dim3(256), 0, stream, n, st, rp, B.perm, diag_caller, B.len, B.diag);
+    hipLaunchKernelGGL(relabel_len, dim3(lb), dim3(256), 0, stream, n, st, rp, B.perm, diag_caller, diag64_caller,
+                       B.len, B.diag, B.diag64);
     SLAQ_LAUNCHED();
     s = exclusive_scan(B.len, n + 1, B.row_ptr, B.bsum, nullptr, nullptr, stream);
     if (s != SLAQ_OK) return s;

@@ -19,6 +19,8 @@ SLAQ_FLAG_CHECK = 1
 SLAQ_FLAG_RELABEL = 2
 SLAQ_FLAG_NO_RELABEL = 4
 SLAQ_RELABEL_MIN_NNZ = 1 << 22
+SLAQ_PREC_FP32 = 0
+SLAQ_PREC_FP64 = 1
 SLAQ_MAX_PROBES = 4096
 SLAQ_MAX_STEPS = 64
 
@@ -42,6 +44,8 @@ SIGNATURES = {
     "slaq_graph_internal": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_i64), _vp, _vp, _vp],
     "slaq_graph_set_schedule": [_vp, _int, _int, _vp],
     "slaq_graph_set_tile": [_vp, _int],
+    "slaq_graph_set_precision": [_vp, _int],
+    "slaq_graph_precision": [_vp, ctypes.POINTER(_int)],
     "slaq_graph_schedule": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
                             ctypes.POINTER(_i64)],
     "slaq_lanczos_workspace": [_vp, _int, _int, ctypes.POINTER(_sz)],
@@ -154,6 +158,14 @@ class Graph:
 
     def set_tile(self, tile_quads):
         _check(lib().slaq_graph_set_tile(self.handle, tile_quads))
+
+    def set_precision(self, precision):
+        _check(lib().slaq_graph_set_precision(self.handle, precision))
+
+    def precision(self):
+        p = _int()
+        _check(lib().slaq_graph_precision(self.handle, ctypes.byref(p)))
+        return p.value
 
     def schedule(self):
         hm, pc, nh, npc = _int(), _int(), _i64(), _i64()

@@ -12,10 +12,13 @@ TOL_VNGE_REL = 1e-4      # relative
 TOL_WAVE_ABS_N = 1e-4    # |gpu - oracle| <= 1e-4 * n (w_t crosses zero)
 
 
-def gpu_run(csr, nv, m, seed, t, laplacian=S.SLAQ_LAP_NORMALIZED, weights=None, check=True, relabel=None):
+def gpu_run(csr, nv, m, seed, t, laplacian=S.SLAQ_LAP_NORMALIZED, weights=None, check=True, relabel=None,
+            precision=None):
     rp, ci = S.to_device(csr)
     w = None if weights is None else torch.from_numpy(np.asarray(weights, dtype=np.float32)).cuda()
     g = S.build_graph(rp, ci, w, laplacian=laplacian, check=check, relabel=relabel)
+    if precision is not None:
+        g.set_precision(precision)
     a, b, s = S.lanczos(g, nv, m, seed)
     th, w2 = S.ritz(a, b, s)
     tt = torch.from_numpy(np.asarray(t, dtype=np.float64)).cuda()

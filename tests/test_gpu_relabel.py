@@ -68,10 +68,9 @@ def test_internal_layout_matches_reference(case):
 
 PARITY = [(c, S.SLAQ_LAP_NORMALIZED) for c in ("chung_lu_iso", "star_iso", "path5_iso", "k9", "edgeless", "rmat14",
                                                   "er_iso")]
-# D - A on bounded degrees (hub graphs under D - A: test_combinatorial_hub_graph;
-# a star under D - A breaks down exactly after 3 steps and its FP32 rounding
-# noise, at the scale of the hub degree, carries the run on -- not a parity case)
-PARITY += [(c, S.SLAQ_LAP_COMBINATORIAL) for c in ("path5_iso", "k9", "edgeless", "er_iso")]
+# D - A (FP64 vectors by default)
+PARITY += [(c, S.SLAQ_LAP_COMBINATORIAL) for c in ("chung_lu_iso", "star_iso", "path5_iso", "k9", "edgeless",
+                                                     "er_iso", "rmat14")]
 
 
 @pytest.mark.parametrize("case,lap", PARITY)
@@ -97,23 +96,26 @@ def test_relabelled_parity(case, lap):
     assert_signature_parity(gpu, ora, csr.n, f"relabel {case}")
 
 
-def test_combinatorial_hub_graph():
-    # D - A of a power-law graph (max degree ~900, spectrum [0, ~1800]): the
+def test_combinatorial_hub_graph_precision():
+    # D - A of a power-law graph (max degree ~900, spectrum [0, ~1800]): its
     # top eigenvalues converge within a few steps and the recurrence, without
-    # reorthogonalization, then loses orthogonality to them -- in FP32 vectors
-    # sooner than in the FP64 oracle, so from step ~10 the coefficients and
-    # the low Ritz values of the two runs part (both are equally far from the
-    # exact low spectrum at m = 15).  What the FP32 path still gives: the first
-    # steps and the heat trace up to t = 0.1 to 1e-4, VNGE of L / tr L only to
-    # 1e-3 (measured 2.6e-4: the FP32 vectors are below the 1e-4 bar here);
-    # the relabelled and the caller-order runs agree with each other.
-    header("combinatorial hub graph")
+    # reorthogonalization, then loses orthogonality to them.  With FP64
+    # vectors (the default for D - A) that happens as late as in the FP64
+    # oracle and the parity bar holds; with FP32 vectors it starts from step
+    # ~10 and the low Ritz values and VNGE move by ~1e-4 relative, while the
+    # first steps and the heat trace up to t = 0.1 still agree to 1e-4.
+    header("combinatorial hub graph, FP64 and FP32 vectors")
     csr = CASES["chung_lu_iso"]()
     nv, m = 20, 15
     lap = S.SLAQ_LAP_COMBINATORIAL
     ora = oracle_run(csr, nv, m, 99, T256, laplacian=lap)
-    runs = [gpu_run(csr, nv, m, 99, T256, laplacian=lap, relabel=r) for r in (True, False)]
+    for r in (True, False):
+        gpu = gpu_run(csr, nv, m, 99, T256, laplacian=lap, relabel=r)
+        np.testing.assert_allclose(gpu["alpha"], ora["alpha"], rtol=1e-7)
+        np.testing.assert_allclose(gpu["beta"], ora["beta"], rtol=1e-7)
+        assert_signature_parity(gpu, ora, csr.n, f"D - A FP64 relabel={r}")
     early = T256 <= 0.1
+    runs = [gpu_run(csr, nv, m, 99, T256, laplacian=lap, relabel=r, precision=S.SLAQ_PREC_FP32) for r in (True, False)]
     for gpu in runs:
         np.testing.assert_allclose(gpu["alpha"][:, :8], ora["alpha"][:, :8], rtol=1e-5)
         np.testing.assert_allclose(gpu["beta"][:, :7], ora["beta"][:, :7], rtol=1e-5)
@@ -122,6 +124,20 @@ def test_combinatorial_hub_graph():
         assert rel.max() <= 1e-4
     # heat counts nodes (h_0 = n): an absolute floor of 1e-4 for its decayed tail
     np.testing.assert_allclose(runs[0]["heat"], runs[1]["heat"], rtol=1e-3, atol=1e-4)
+
+
+@pytest.mark.parametrize("relabel", [False, True])
+def test_fp64_vectors_match_the_oracle_tightly(relabel):
+    # the same kernels in FP64 differ from the FP64 oracle only in summation
+    # order: a tight pin on the SpMM / update / reduction arithmetic
+    header(f"FP64 vectors, normalized, relabel={relabel}")
+    csr = CASES["chung_lu_iso"]()
+    gpu = gpu_run(csr, 36, 15, 4, T256, relabel=relabel, precision=S.SLAQ_PREC_FP64)
+    ora = oracle_run(csr, 36, 15, 4, T256)
+    np.testing.assert_allclose(gpu["alpha"], ora["alpha"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gpu["beta"], ora["beta"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gpu["heat"], ora["heat"], rtol=1e-9)
+    assert abs(gpu["vnge"] - ora["vnge"]) <= 1e-9 * abs(ora["vnge"])
 
 
 def test_relabelled_weighted():
