@@ -59,6 +59,22 @@ def update_algorithmic_bytes(n, n_act, nv):
     return 4 * n + 12 * n_act * nv
 
 
+TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "spmm_rmat22_traffic.json")
+
+
+def measured_traffic(workload):
+    """HBM bytes per SpMM-stage launch from the committed FETCH_SIZE /
+    WRITE_SIZE record, or None when there is none for this workload or the
+    kernel sources changed since it was taken."""
+    from paper_2003_01282_amd.profsum import kernel_sources_digest
+    if workload != "rmat22" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = json.load(open(TRAFFIC_RECORD))
+    if rec.get("digest") != kernel_sources_digest():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(csr, nv, m, seed, budget_s=25.0):
     """The FP64 oracle's Lanczos loop on a probe subset of the same graph."""
     from oracle import slq as O
@@ -279,6 +295,22 @@ def bench_closure(args):
     print(json.dumps(out_line), flush=True)
 
 
+def line_probe():
+    """Random 128-B-line read rate for working sets of 2 MiB to 4 GiB (the
+    ceiling of gathers that miss L2), from libslaq_probe.so."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2003_01282_amd",
+                                   "libslaq_probe.so"))
+    mib = [2, 8, 16, 32, 64, 128, 256, 512, 1024, 4096]
+    sizes = (ctypes.c_size_t * len(mib))(*[x << 20 for x in mib])
+    out = (ctypes.c_double * len(mib))()
+    rc = lib.slaq_line_probe(sizes, len(mib), out)
+    if rc != 0:
+        raise SystemExit(f"slaq_line_probe failed: hipError {rc}")
+    print(json.dumps({"probe": "random 128-byte line reads", "unit": "TB/s",
+                      "working_set_MiB": mib, "rate": [round(v, 3) for v in out]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,7 +327,11 @@ def main():
     ap.add_argument("--closure-epochs", type=int, default=12)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (calibrates hardware byte counters)")
+    ap.add_argument("--line-probe", action="store_true",
+                    help="only measure random 128-byte-line read throughput against working-set size")
     args = ap.parse_args()
+    if args.line_probe:
+        return line_probe()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(probe sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
@@ -429,7 +465,8 @@ def main():
                    "generator": spec, "n_nonisolated": n_act, "schedule": graphs[0].schedule(),
                    "tile_quads": args.tile},
         "roofline": {"bound": "hbm", "kernel": "spmm_pieces+spmm_rows+spmm_heavy", "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(args.workload),
                      "bytes_per_launch": spmm_bytes, "avg_launch_ms": spmm_ms},
         "spmm_hbm_gbs": achieved,
         "update_gbs": upd_gbs,

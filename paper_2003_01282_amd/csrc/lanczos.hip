@@ -35,11 +35,10 @@ namespace slaq {
 
 constexpr int kPieceUnroll = 8;  // gathers in flight per group in the piece kernel
 
-// breakdown threshold relative to the spectral bound: above the rounding
-// noise of the vectors' precision
-template <typename V> constexpr double eps_breakdown();
-template <> constexpr double eps_breakdown<float>() { return 1e-6; }
-template <> constexpr double eps_breakdown<double>() { return 1e-10; }
+// breakdown threshold relative to the spectral bound (above the rounding
+// noise of FP32 vectors; the same for FP64 ones, so both stop where the FP64
+// reference recurrence stops)
+constexpr double kEpsBreakdown = 1e-6;
 
 template <typename V>
 struct alignas(16) Quad {
@@ -768,7 +767,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
                    hipLaunchKernelGGL(finalize_b<V>, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,
-                                      g->stats, mode, eps_breakdown<V>(), ps, beta, steps, coef));
+                                      g->stats, mode, kEpsBreakdown, ps, beta, steps, coef));
         SLAQ_LAUNCHED();
         if (j < m) {
             const int t = cur;

@@ -1,18 +1,41 @@
-"""Summarize rocprofv3 CSV output per kernel (a profiling helper, not the path).
+"""Summaries of rocprofv3 CSV output (a profiling helper, not the path).
 
     python -m paper_2003_01282_amd.profsum stats <dir>      # --kernel-trace --stats
     python -m paper_2003_01282_amd.profsum pmc <dir>        # --pmc runs
+    python -m paper_2003_01282_amd.profsum traffic <fetch_dir> <write_dir> <copy_bytes> <out.json>
 
 `stats` prints calls and average/total duration per kernel from
 *_kernel_stats.csv; `pmc` averages every counter column of
 *_counter_collection.csv per kernel (values per dispatch, as rocprofv3
-reports them: FETCH_SIZE / WRITE_SIZE in KiB).
+reports them: FETCH_SIZE / WRITE_SIZE in KiB).  `traffic` turns a FETCH_SIZE
+run and a WRITE_SIZE run of bench.py (with --copy-probe-mb) into HBM bytes
+per launch of the SpMM stage: each counter is scaled by the ratio of the
+known bytes of the device-to-device copy dispatches (copy_bytes in total) to
+what the same counter read for them, and the record is stamped with a digest
+of the kernel sources, so a later source change voids it.
 """
 import csv
 import glob
+import hashlib
+import json
 import os
 import sys
 from collections import defaultdict
+from pathlib import Path
+
+SPMM_STAGE = ("spmm_pieces", "spmm_rows", "spmm_heavy")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+KERNEL_SOURCES = ("common.hpp", "graph.hip", "relabel.hip", "lanczos.hip")
+
+
+def kernel_sources_digest():
+    """sha256 over the sources the SpMM stage and its data layout come from."""
+    h = hashlib.sha256()
+    csrc = Path(__file__).resolve().parent / "csrc"
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        h.update((csrc / name).read_bytes())
+    return h.hexdigest()
 
 
 def short(name, width=60):
@@ -20,29 +43,64 @@ def short(name, width=60):
     return name if len(name) <= width else name[: width - 3] + "..."
 
 
-def stats(d):
+def stats(d, out=sys.stdout):
     f = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
     rows = list(csv.DictReader(open(f)))
-    print(f"# {f}")
-    print(f"{'kernel':62s} {'calls':>6s} {'avg_us':>12s} {'total_ms':>10s} {'pct':>6s}")
+    print(f"{'kernel':62s} {'calls':>6s} {'avg_us':>12s} {'total_ms':>10s} {'pct':>6s}", file=out)
     for r in rows:
         print(f"{short(r['Name']):62s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:12.2f} "
-              f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}")
+              f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}", file=out)
 
 
-def pmc(d):
-    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    for f in files:
-        rows = list(csv.DictReader(open(f)))
-        acc = defaultdict(lambda: defaultdict(list))
-        for r in rows:
+def pmc_table(d):
+    """{kernel: {counter: [per-dispatch values]}} over every counter file under d."""
+    acc = defaultdict(lambda: defaultdict(list))
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
             k = short(r.get("Kernel_Name", r.get("Kernel-Name", "?")))
             acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
-        print(f"# {f}")
-        for k, cs in acc.items():
-            for c, v in cs.items():
-                print(f"{k:62s} {c:16s} dispatches {len(v):4d} avg {sum(v) / len(v):16.1f}")
+    return acc
+
+
+def pmc(d, out=sys.stdout):
+    for k, cs in pmc_table(d).items():
+        for c, v in cs.items():
+            print(f"{k:62s} {c:16s} dispatches {len(v):4d} avg {sum(v) / len(v):16.1f}", file=out)
+
+
+def _find(table, stem):
+    for k, cs in table.items():
+        if stem in k:
+            return cs
+    raise KeyError(stem)
+
+
+def traffic(fetch_dir, write_dir, copy_bytes, out_json):
+    rec = {"kernels": {}, "digest": kernel_sources_digest()}
+    per_launch = 0.0
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        t = pmc_table(d)
+        copy = _find(t, COPY_KERNEL)[counter]
+        scale = copy_bytes / (sum(copy) * 1024.0)  # true bytes per counted byte
+        rec[f"{counter}_scale"] = scale
+        for k in SPMM_STAGE:
+            v = _find(t, f"slaq::{k}")[counter]
+            kib = sum(v) / len(v)
+            rec["kernels"].setdefault(k, {})[counter + "_KiB"] = kib
+            rec["kernels"][k][counter + "_bytes"] = kib * 1024.0 * scale
+            per_launch += kib * 1024.0 * scale
+    rec["bytes_per_launch"] = per_launch
+    Path(out_json).write_text(json.dumps(rec, indent=1) + "\n")
+    print(json.dumps(rec, indent=1))
 
 
 if __name__ == "__main__":
-    {"stats": stats, "pmc": pmc}[sys.argv[1]](sys.argv[2])
+    cmd = sys.argv[1]
+    if cmd == "stats":
+        stats(sys.argv[2])
+    elif cmd == "pmc":
+        pmc(sys.argv[2])
+    elif cmd == "traffic":
+        traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5])
+    else:
+        raise SystemExit(f"unknown command {cmd}")
