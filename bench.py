@@ -432,6 +432,28 @@ def main():
     upd_ms = stages["update"]["avg_ms"]
     upd_gbs = update_algorithmic_bytes(csr.n, n_act, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
 
+    # the variance-reduced estimate (control variates tr L, tr L^2; fitted
+    # coefficients), timed once after the timed region: it is not part of the
+    # step above
+    vr = None
+    if args.workload in ("rmat22", "chung_lu"):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        tr = torch.empty(2, dtype=torch.float64, device=dev)
+        heat_cv = torch.empty_like(heat)
+        wave_cv = torch.empty_like(wave)
+        H_cv = torch.empty_like(H)
+        ev[0].record()
+        S.graph_traces(graphs[0], out=tr)
+        ev[1].record()
+        S.signature_cv(theta, tau2, csr.n, tr, tgrid, S.SLAQ_SIG_HEAT, S.SLAQ_CV_FITTED, out=heat_cv)
+        S.signature_cv(theta, tau2, csr.n, tr, tgrid, S.SLAQ_SIG_WAVE, S.SLAQ_CV_FITTED, out=wave_cv)
+        S.vnge_cv(graphs[0], theta, tau2, tr, S.SLAQ_CV_FITTED, out=H_cv)
+        ev[2].record()
+        torch.cuda.synchronize()
+        vr = {"mode": "fitted", "traces_ms": ev[0].elapsed_time(ev[1]), "cv_quadrature_ms": ev[1].elapsed_time(ev[2]),
+              "tr_L": float(tr[0]), "tr_L2": float(tr[1]), "vnge": float(H[0]), "vnge_cv": float(H_cv[0])}
+        log(f"variance reduction: {vr}")
+
     h = heat.cpu().numpy()
     sanity = bool(np.all(np.isfinite(h)) and np.all(np.diff(h) <= 1e-9 * csr.n) and 0 < h[-1] < csr.n)
 
@@ -472,6 +494,7 @@ def main():
         "update_gbs": upd_gbs,
         "stages": stages,
         "heat_sane": sanity,
+        "variance_reduction": vr,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -159,6 +159,38 @@ slaq_status slaq_graph_precision(slaq_graph_t g, int* precision);
 slaq_status slaq_graph_internal(slaq_graph_t g, int* relabeled, int64_t* n_rows, int32_t* perm,
                                 int64_t* row_ptr, int32_t* col_idx);
 
+/* Variance reduction of the trace estimate (§3.1, last paragraph: a "2-term
+ * polynomial variance reduction"; the paper gives no formula).  The two terms
+ * are control variates with exact means: Z1_p = n q_p^T L q_p (mean tr L) and
+ * Z2_p = n q_p^T L^2 q_p (mean tr L^2), which the Gauss rule of each probe
+ * gives exactly for m >= 2 as n sum_k tau2 theta and n sum_k tau2 theta^2.
+ * With X_p = n sum_k tau2 f(theta) the estimate is
+ *   mean(X) - g1 (mean(Z1) - tr L) - g2 (mean(Z2) - tr L^2).
+ * SLAQ_CV_NONE: g = 0 (plain SLQ).  SLAQ_CV_TAYLOR: the degree-2 Taylor
+ * polynomial of f at 0 (heat (-t, t^2/2), wave (0, -t^2/2), VNGE (1/c, -1/c^2)
+ * from -x ln x ~ x - x^2 on x = lambda / c): unbiased, for small t only
+ * (its coefficients grow like t^2 and multiply the probes' spread of Z2).
+ * SLAQ_CV_FITTED: least-squares regression of X on (Z1, Z2) over the probes
+ * (bias O(1/nv)); fewer than 3 probes or no spread in Z1 -> plain; 3 probes,
+ * no spread in Z2 or a 2x2 system with det <= 1e-10 S11 S22 -> Z1 alone. */
+enum { SLAQ_CV_NONE = 0, SLAQ_CV_TAYLOR = 1, SLAQ_CV_FITTED = 2 };
+
+/* tr L and tr L^2 = sum_ij L_ij^2 of the graph's Laplacian (§2), FP64, into
+ * traces[0..1] (device), one O(nnz) pass on `stream` (self-loops taken
+ * literally; isolated nodes have zero rows).  Uses the handle's scratch:
+ * calls on one graph must not overlap. */
+slaq_status slaq_graph_traces(slaq_graph_t g, double* traces, void* stream);
+
+/* Variance-reduced heat / wave trace at nt times (as slaq_signature, plus the
+ * device traces[2] of slaq_graph_traces and a SLAQ_CV_* mode). */
+slaq_status slaq_signature_cv(const double* theta, const double* tau2, int nv, int m, int64_t n,
+                              const double* traces, const double* t, int nt, int kind, int mode,
+                              double* out, void* stream);
+
+/* Variance-reduced VNGE (as slaq_vnge, c = the graph's tr L of §2.1). */
+slaq_status slaq_vnge_cv(slaq_graph_t g, const double* theta, const double* tau2, int nv, int m,
+                         const double* traces, int mode, double* out, void* stream);
+
 /* Frees the host handle (never caller memory). */
 slaq_status slaq_graph_destroy(slaq_graph_t g);
 

@@ -78,6 +78,9 @@ constexpr int kColRanges = 8;
 // 1024, 16 buckets per octave above; lengths < 2^31), in chunks of
 // kSortChunk caller ids per workgroup.
 constexpr int kDegBuckets = 1024 + 16 * 21;
+
+// Partial sums of slaq_graph_traces (two doubles per workgroup).
+constexpr int kTraceBlocks = 1024;
 constexpr int kSortChunk = 4096;
 
 }  // namespace slaq
@@ -105,6 +108,7 @@ struct slaq_graph_s {
     int64_t* segoff;         // [kColRanges * max_heavy + 1]: first piece of (x, h), x-major
     long long* segcnt;       // [kColRanges * max_heavy] pieces of (x, h) before the scan
     long long* scanbuf;      // block sums of the segment scan
+    double* trace_part;      // [2 * kTraceBlocks] partials of slaq_graph_traces
     int64_t max_heavy;       // capacity of hrow / hoff / segk (stride of the x-major arrays)
     int heavy_min;
     int piece;

@@ -402,7 +402,7 @@ slaq_status exclusive_scan(const long long* in, int64_t len, int64_t* out, long 
 struct ScratchLayout {
     size_t off_stats, off_part, off_counts, off_hrow, off_hoff, off_bounds, off_segk, off_cnt, off_segoff, off_bsum,
         off_perm, off_inv, off_rp2, off_col2, off_w2, off_tmp, off_diag2, off_d64, off_d64r, off_len, off_sortcnt,
-        off_sortoff, total;
+        off_sortoff, off_tpart, total;
     int64_t nplan, max_heavy, sort_chunks;
 };
 
@@ -446,6 +446,7 @@ static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     L.off_len = take(sizeof(long long) * ((size_t)n + 1));
     L.off_sortcnt = take(sizeof(long long) * sort_len);
     L.off_sortoff = take(sizeof(int64_t) * sort_len);
+    L.off_tpart = take(sizeof(double) * 2 * kTraceBlocks);
     L.total = off;
     return L;
 }
@@ -565,6 +566,7 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->segcnt = (long long*)(base + SL.off_cnt);
     g->segoff = (int64_t*)(base + SL.off_segoff);
     g->scanbuf = (long long*)(base + SL.off_bsum);
+    g->trace_part = (double*)(base + SL.off_tpart);
     g->max_heavy = SL.max_heavy;
     g->heavy_min = kDefaultHeavyMin;
     g->piece = kDefaultPiece;

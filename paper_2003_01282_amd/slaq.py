@@ -21,6 +21,9 @@ SLAQ_FLAG_NO_RELABEL = 4
 SLAQ_RELABEL_MIN_NNZ = 1 << 22
 SLAQ_PREC_FP32 = 0
 SLAQ_PREC_FP64 = 1
+SLAQ_CV_NONE = 0
+SLAQ_CV_TAYLOR = 1
+SLAQ_CV_FITTED = 2
 SLAQ_MAX_PROBES = 4096
 SLAQ_MAX_STEPS = 64
 
@@ -42,6 +45,9 @@ SIGNATURES = {
                         ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
     "slaq_graph_destroy": [_vp],
     "slaq_graph_internal": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_i64), _vp, _vp, _vp],
+    "slaq_graph_traces": [_vp, _vp, _vp],
+    "slaq_signature_cv": [_vp, _vp, _int, _int, _i64, _vp, _vp, _int, _int, _int, _vp, _vp],
+    "slaq_vnge_cv": [_vp, _vp, _vp, _int, _int, _vp, _int, _vp, _vp],
     "slaq_graph_set_schedule": [_vp, _int, _int, _vp],
     "slaq_graph_set_tile": [_vp, _int],
     "slaq_graph_set_precision": [_vp, _int],
@@ -275,6 +281,35 @@ def vnge(g, theta, tau2, out=None, stream=None):
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=theta.device)
     _check(lib().slaq_vnge(g.handle, _ptr(theta), _ptr(tau2), nv, m, _ptr(out), _stream(stream)))
+    return out
+
+
+def graph_traces(g, out=None, stream=None):
+    """slaq_graph_traces -> double[2] (tr L, tr L^2)."""
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=g._keep["row_ptr"].device)
+    _check(lib().slaq_graph_traces(g.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def signature_cv(theta, tau2, n, traces, t, kind=SLAQ_SIG_HEAT, mode=SLAQ_CV_FITTED, out=None, stream=None):
+    """slaq_signature_cv -> double[nt] (variance-reduced heat or wave trace)."""
+    nv, m = theta.shape
+    _dev(t, torch.float64, "t")
+    if out is None:
+        out = torch.empty(t.numel(), dtype=torch.float64, device=theta.device)
+    _check(lib().slaq_signature_cv(_ptr(theta), _ptr(tau2), nv, m, n, _ptr(traces), _ptr(t), t.numel(), kind, mode,
+                                   _ptr(out), _stream(stream)))
+    return out
+
+
+def vnge_cv(g, theta, tau2, traces, mode=SLAQ_CV_FITTED, out=None, stream=None):
+    """slaq_vnge_cv -> double[1]."""
+    nv, m = theta.shape
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=theta.device)
+    _check(lib().slaq_vnge_cv(g.handle, _ptr(theta), _ptr(tau2), nv, m, _ptr(traces), mode, _ptr(out),
+                              _stream(stream)))
     return out
 
 
