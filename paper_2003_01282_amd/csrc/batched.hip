@@ -504,8 +504,8 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         return SLAQ_ERR_HIP;
     }
     if (hipMemcpy(b->order_dev, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(b->order_dev);
-        hipFree(b->queues_dev);
+        (void)hipFree(b->order_dev);
+        (void)hipFree(b->queues_dev);
         delete b;
         set_error("copy of the batch order failed");
         return SLAQ_ERR_HIP;
@@ -576,8 +576,8 @@ slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, doubl
     const bool same = b->exec && std::memcmp(key, b->exec_key, sizeof(key)) == 0 && b->exec_seed == seed;
     if (!same) {
         if (b->exec) {
-            hipGraphExecDestroy(b->exec);
-            hipGraphDestroy(b->graph);
+            (void)hipGraphExecDestroy(b->exec);
+            (void)hipGraphDestroy(b->graph);
             b->exec = nullptr;
         }
         if (!b->cap) SLAQ_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
@@ -644,11 +644,11 @@ slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, d
         if (blocks_out) blocks_out[k] = best.block;
         if (best_ms_out) best_ms_out[k] = best_ms;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (b->exec) {  // schedule changed: drop the captured graph
-        hipGraphExecDestroy(b->exec);
-        hipGraphDestroy(b->graph);
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
     }
     return SLAQ_OK;
@@ -657,12 +657,12 @@ slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, d
 slaq_status slaq_batch_destroy(slaq_batch_t b) {
     if (!b) return SLAQ_OK;
     if (b->exec) {
-        hipGraphExecDestroy(b->exec);
-        hipGraphDestroy(b->graph);
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
     }
-    if (b->cap) hipStreamDestroy(b->cap);
-    hipFree(b->order_dev);
-    hipFree(b->queues_dev);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    (void)hipFree(b->order_dev);
+    (void)hipFree(b->queues_dev);
     delete b;
     return SLAQ_OK;
 }

@@ -593,13 +593,13 @@ slaq_status slaq_closure_create(int d_in, int hidden, int nt, uint64_t seed, voi
 
 slaq_status slaq_closure_destroy(slaq_closure_t c) {
     if (!c) return SLAQ_OK;
-    hipFree(c->w);
-    hipFree(c->wb);
-    hipFree(c->grad);
-    hipFree(c->m1);
-    hipFree(c->m2);
-    hipFree(c->off_dev);
-    hipFree(c->fan_dev);
+    (void)hipFree(c->w);
+    (void)hipFree(c->wb);
+    (void)hipFree(c->grad);
+    (void)hipFree(c->m1);
+    (void)hipFree(c->m2);
+    (void)hipFree(c->off_dev);
+    (void)hipFree(c->fan_dev);
     delete c;
     return SLAQ_OK;
 }

@@ -4,7 +4,7 @@
 //
 // The vectors are kept unnormalized: R_j = beta_{j-1} q_j, R_1 = v (the +-1
 // probe), sigma_j = 1/||R_j||.  Per step j
-//   spmm_pieces   partial products sum_k A_ik D_c R_j[c] of the pieces of heavy rows
+//   spmm_pieces   partial sums sum_k A_ik X_j[k] of the pieces of heavy rows
 //   spmm_rows     w = sigma_j L R_j - tau_{j-1} R_{j-1}  (tau_{j-1} = beta_{j-1} sigma_{j-1})
 //                 and FP64 partial sums of R_j . w
 //   finalize_a    alpha_j = sigma_j sum(R_j . w);  a_j = alpha_j sigma_j
@@ -20,6 +20,14 @@
 // hubs, where FP32 vectors lose orthogonality to the converged top of the
 // spectrum within a few steps).  A "quad" is 16 bytes of a probe row: 4 floats
 // or 2 doubles; a lane holds one quad.
+//
+// Normalized Laplacian: the probe blocks are stored in the scaled basis
+// X_j = D^-1/2 R_j (per row, with the same D^-1/2 the kernels read), so the
+// SpMM sums plain neighbour rows, (A X_j)_i, with no per-nonzero scale; the
+// row epilogue forms D^-1/2 w = sigma (X_i - dinv_i^2 (A X_j)_i) - tau X_{j-1,i}
+// (which is D^-1/2 times sigma (L R_j)_i - tau R_{j-1,i}), the update keeps its
+// form, and the dot products weight row i by 1/dinv_i^2 so that they are the
+// ones of R: R_j.w = sum_i X_i (D^-1/2 w)_i / dinv_i^2.  D - A needs no scale.
 //
 // Isolated nodes have zero rows and columns in L, so on them every R_j is a
 // multiple of the probe: R_j[i] = rho_j v[i] with rho_1 = 1, rho_0 = 0 and
@@ -157,10 +165,11 @@ __global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double 
 }
 
 // R_1[i][p] = +-1 (bit (p mod 64) of splitmix64(seed, 64 id + p div 64), id
-// the caller's id of internal row i) on rows with data; padding probes are 0.
+// the caller's id of internal row i) on rows with data, stored as X_1 = dinv_i
+// R_1 for the normalized Laplacian; padding probes are 0.
 // One quad per thread, rows strided.
 template <typename V>
-__global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__ st, int nv, int F,
+__global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__ st, int laplacian, int nv, int F,
                                                   int rows_per_sweep, uint64_t seed,
                                                   const V* __restrict__ diag,
                                                   const int32_t* __restrict__ perm, Quad<V>* __restrict__ R) {
@@ -177,10 +186,11 @@ __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__
         if (diag[i] == V(0)) continue;
         const uint64_t id = perm ? (uint64_t)perm[i] : (uint64_t)i;
         const uint64_t z = splitmix64(seed, 64ull * id + word);
+        const V one = laplacian == SLAQ_LAP_NORMALIZED ? diag[i] : V(1);  // X_1 = D^-1/2 v
         Quad<V> v;
 #pragma unroll
         for (int c = 0; c < E; ++c) {
-            const V sgn = ((z >> (bit0 + c)) & 1ull) ? V(-1) : V(1);
+            const V sgn = ((z >> (bit0 + c)) & 1ull) ? -one : one;
             v.v[c] = (p0 + c < nv) ? sgn : V(0);
         }
         R[i * F + quad] = v;
@@ -202,9 +212,7 @@ __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t 
         V sl = V(0);
         if (gl < cnt) {
             cl = col[kb + gl];
-            V sc = WEIGHTED ? (V)w[kb + gl] : V(1);
-            if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[cl];
-            sl = sc;
+            sl = WEIGHTED ? (V)w[kb + gl] : V(1);
         }
         int u = 0;
         for (; u + 4 <= cnt; u += 4) {
@@ -284,9 +292,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
             V sl = V(0);
             if (lane < cnt) {
                 cl = col[kb + lane];
-                V sc = WEIGHTED ? (V)w[kb + lane] : V(1);
-                if (MODE == SLAQ_LAP_NORMALIZED) sc *= diag[cl];
-                sl = sc;
+                sl = WEIGHTED ? (V)w[kb + lane] : V(1);
             }
             const int rounds = (cnt + K - 1) / K;
             int r = 0;
@@ -326,8 +332,11 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
     }
 }
 
-// Row epilogue shared by the row and heavy-row kernels: w_i = sigma (L R_j)_i
-// - tau R_{j-1}[i], stored; accumulates the FP64 products R_j[i] * w_i in s1.
+// Row epilogue shared by the row and heavy-row kernels: with acc = (A X_j)_i
+// (normalized, scaled basis) or (A R_j)_i (D - A) it stores
+//   normalized: D^-1/2 w_i = sigma (X_i - dinv_i^2 acc) - tau X_{j-1,i}
+//   D - A:      w_i       = sigma (D_ii R_i - acc)     - tau R_{j-1,i}
+// and accumulates R_j[i] * w_i in FP64 (normalized: X_i (D^-1/2 w)_i / dinv_i^2).
 template <int MODE, typename V>
 __device__ __forceinline__ void row_epilogue(int64_t i, const Quad<V>& acc, const V* __restrict__ diag,
                                              const Quad<V>* __restrict__ R, const Quad<V>* __restrict__ Rp,
@@ -336,22 +345,30 @@ __device__ __forceinline__ void row_epilogue(int64_t i, const Quad<V>& acc, cons
     constexpr int E = Quad<V>::E;
     const Quad<V> ri = R[i * F + quad];
     const V di = diag[i];
+    const double dd = (double)di, d2 = dd * dd;
+    // per-row arithmetic in FP64, one rounding to the storage precision (the
+    // scale dinv_i^2 stays exact, so the scaled operator stays symmetric)
+    Quad<V> rq = qzero<V>();
+    if (has_prev) rq = Rp[i * F + quad];
     Quad<V> wi;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        // (L R_j)_i
-        const V lr = MODE == SLAQ_LAP_NORMALIZED ? vfma(-di, acc.v[e], ri.v[e]) : vfma(di, ri.v[e], -acc.v[e]);
-        wi.v[e] = sg.v[e] * lr;
-    }
-    if (has_prev) {
-        const Quad<V> rq = Rp[i * F + quad];
-#pragma unroll
-        for (int e = 0; e < E; ++e) wi.v[e] = vfma(-tp.v[e], rq.v[e], wi.v[e]);
+        const double x = (double)ri.v[e], a = (double)acc.v[e];
+        const double lr = MODE == SLAQ_LAP_NORMALIZED ? fma(-d2, a, x) : fma(dd, x, -a);
+        double wv = (double)sg.v[e] * lr;
+        if (has_prev) wv = fma(-(double)tp.v[e], (double)rq.v[e], wv);
+        wi.v[e] = (V)wv;
     }
     W[i * F + quad] = wi;
     // FP32: products of two floats are exact in double
+    if (MODE == SLAQ_LAP_NORMALIZED) {
+        const double wgt = di != V(0) ? 1.0 / d2 : 0.0;  // zero weight sum: no data
 #pragma unroll
-    for (int e = 0; e < E; ++e) s1[e] = fma((double)ri.v[e], (double)wi.v[e], s1[e]);
+        for (int e = 0; e < E; ++e) s1[e] = fma((double)ri.v[e] * (double)wi.v[e], wgt, s1[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) s1[e] = fma((double)ri.v[e], (double)wi.v[e], s1[e]);
+    }
 }
 
 // Heavy rows: one wave per row sums the row's pieces (all column ranges, the
@@ -467,10 +484,12 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
     block_reduce_store<E>(s1, part, nb, F, G, K, ld, tile, TQ);
 }
 
-// R_{j+1} = w - a_j R_j on rows with data (stored when `store`), partial
-// sums of ||R_{j+1}||^2.  Same wave/group layout as spmm_rows.
+// R_{j+1} = w - a_j R_j on rows with data (stored when `store`; in the scaled
+// basis for the normalized Laplacian), partial sums of ||R_{j+1}||^2.  Same
+// wave/group layout as spmm_rows.
 template <typename V>
-__global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st, const V* __restrict__ diag,
+__global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st, int laplacian,
+                                              const V* __restrict__ diag,
                                               const Quad<V>* __restrict__ W, const Quad<V>* __restrict__ R,
                                               const V* __restrict__ coef, int store,
                                               Quad<V>* __restrict__ Rn, double* __restrict__ part, int nb,
@@ -505,8 +524,10 @@ __global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st,
 #pragma unroll
             for (int e = 0; e < E; ++e) r.v[e] = vfma(-a.v[e], rv.v[e], wv.v[e]);
             if (store) Rn[i * F + quad] = r;
+            // normalized: ||R_{j+1}||^2 = sum_i X_{j+1,i}^2 / dinv_i^2
+            const double wgt = laplacian == SLAQ_LAP_NORMALIZED ? 1.0 / ((double)d * (double)d) : 1.0;
 #pragma unroll
-            for (int e = 0; e < E; ++e) s2[e] = fma((double)r.v[e], (double)r.v[e], s2[e]);
+            for (int e = 0; e < E; ++e) s2[e] = fma((double)r.v[e] * (double)r.v[e], wgt, s2[e]);
         }
     }
     block_reduce_store<E>(s2, part, nb, F, G, K, ld, tile, TQ);
@@ -719,7 +740,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
     SLAQ_LAUNCHED();
     int rps = 0;
     const int sgrid = sweep_grid(g->n, L.F, &rps);
-    hipLaunchKernelGGL(probe_init<V>, dim3(sgrid), dim3(256), 0, st, g->stats, nv, L.F, rps, seed, diag, g->perm,
+    hipLaunchKernelGGL(probe_init<V>, dim3(sgrid), dim3(256), 0, st, g->stats, mode, nv, L.F, rps, seed, diag, g->perm,
                        Rb[0]);
     SLAQ_LAUNCHED();
 
@@ -762,7 +783,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
         SLAQ_LAUNCHED();
         SLAQ_TIMED("update", st,
                    hipLaunchKernelGGL(update<V>, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->stats,
-                                      diag, Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F,
+                                      mode, diag, Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F,
                                       L.Gu, L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
