@@ -142,7 +142,13 @@ struct RelabelBuffers {
     long long* sort_cnt; // [kDegBuckets * chunks]
     int64_t* sort_off;   // [kDegBuckets * chunks]
     long long* bsum;     // scan partials
+    int64_t* chunk_off;  // [n + 1] first chunk of each long row
+    int32_t* ccnt;       // [max_chunks * 8] entries per (chunk, range)
+    int32_t* coff;       // [max_chunks * 8] first position per (chunk, range) within the row
 };
+
+// Upper bound of the chunks the relabelling cuts long rows into.
+inline int64_t relabel_max_chunks(int64_t nnz) { return nnz / 256 + nnz / 1024 + 1; }
 
 // Relabels the caller's CSR into B (sets st->n_rows and the range bounds).
 slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp, const int32_t* col,

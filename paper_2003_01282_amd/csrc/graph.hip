@@ -402,7 +402,7 @@ slaq_status exclusive_scan(const long long* in, int64_t len, int64_t* out, long 
 struct ScratchLayout {
     size_t off_stats, off_part, off_counts, off_hrow, off_hoff, off_bounds, off_segk, off_cnt, off_segoff, off_bsum,
         off_perm, off_inv, off_rp2, off_col2, off_w2, off_tmp, off_diag2, off_d64, off_d64r, off_len, off_sortcnt,
-        off_sortoff, off_tpart, total;
+        off_sortoff, off_tpart, off_choff, off_ccnt, off_coff, total;
     int64_t nplan, max_heavy, sort_chunks;
 };
 
@@ -447,6 +447,9 @@ static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     L.off_sortcnt = take(sizeof(long long) * sort_len);
     L.off_sortoff = take(sizeof(int64_t) * sort_len);
     L.off_tpart = take(sizeof(double) * 2 * kTraceBlocks);
+    L.off_choff = take(sizeof(int64_t) * ((size_t)n + 1));
+    L.off_ccnt = take(sizeof(int32_t) * kColRanges * (size_t)relabel_max_chunks(nnz));
+    L.off_coff = take(sizeof(int32_t) * kColRanges * (size_t)relabel_max_chunks(nnz));
     L.total = off;
     return L;
 }
@@ -593,6 +596,9 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
         B.sort_cnt = (long long*)(base + SL.off_sortcnt);
         B.sort_off = (int64_t*)(base + SL.off_sortoff);
         B.bsum = g->scanbuf;
+        B.chunk_off = (int64_t*)(base + SL.off_choff);
+        B.ccnt = (int32_t*)(base + SL.off_ccnt);
+        B.coff = (int32_t*)(base + SL.off_coff);
         const slaq_status rs = relabel_build(B, n, row_ptr, col_idx, weights, dinv_out, d64, stats, g->bounds, st);
         if (rs != SLAQ_OK) {
             delete g;

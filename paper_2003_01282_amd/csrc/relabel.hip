@@ -23,9 +23,10 @@
 //   relabel_len    row lengths and diagonal scale (FP32 and FP64) in label order
 //   scan           row offsets of the relabelled CSR
 //   range bounds   base(x), x = 0..8
-//   relabel_rows   one wave per row: columns mapped to labels (one gather
-//                  each) and listed range by range (caller order within a
-//                  range), weights alongside
+//   relabel_short_rows / relabel_rows / long_row_*   thread per row up to 32
+//                  entries, wave per row up to 1024, chunks of 256 above (count,
+//                  offsets, place): columns mapped to labels and listed range by
+//                  range (caller order within a range), weights alongside
 #include "common.hpp"
 
 namespace slaq {
@@ -139,6 +140,63 @@ __device__ __forceinline__ int range_of(int64_t c, const int64_t (&bnd)[kColRang
     return x;
 }
 
+// Short rows (at most kShortRow entries): one thread per row, so a wave keeps
+// 64 rows' label gathers in flight.  Pass 1 maps and counts per range, pass 2
+// maps again (the labels are in L2 by then) and places the entries range by
+// range in caller order: the same layout as the wave kernel below.
+constexpr int kShortRow = 32;
+// Long rows (more than kBigRow entries): cut into chunks of kRelabelChunk
+// entries that workgroups process in parallel (one wave walking a hub row of
+// 10^5 entries would be the critical path of the build).
+constexpr int kBigRow = 1024;
+constexpr int kRelabelChunk = 256;
+
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(256) relabel_short_rows(const GraphStats* __restrict__ st,
+                                                          const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const float* __restrict__ w,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ inv,
+                                                          const int64_t* __restrict__ bounds,
+                                                          const int64_t* __restrict__ rp2,
+                                                          int32_t* __restrict__ col2, float* __restrict__ w2) {
+    const int64_t nr = st->n_rows;
+    int64_t bnd[kColRanges];
+#pragma unroll
+    for (int r = 0; r < kColRanges; ++r) bnd[r] = bounds[r];
+    for (int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; L < nr;
+         L += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = perm[L], s = rp[o], e = rp[o + 1];
+        if (e - s > kShortRow) continue;
+        int cnt[kColRanges];
+#pragma unroll
+        for (int r = 0; r < kColRanges; ++r) cnt[r] = 0;
+        for (int64_t k = s; k < e; ++k) {
+            const int x = range_of(inv[col[k]], bnd);
+#pragma unroll
+            for (int r = 0; r < kColRanges; ++r) cnt[r] += x == r ? 1 : 0;
+        }
+        int64_t pos[kColRanges];
+        int64_t run = rp2[L];
+#pragma unroll
+        for (int r = 0; r < kColRanges; ++r) {
+            pos[r] = run;
+            run += cnt[r];
+        }
+        for (int64_t k = s; k < e; ++k) {
+            const int32_t c = inv[col[k]];
+            const int x = range_of(c, bnd);
+            int64_t p = 0;
+#pragma unroll
+            for (int r = 0; r < kColRanges; ++r)
+                if (x == r) p = pos[r]++;
+            col2[p] = c;
+            if (WEIGHTED) w2[p] = w[k];
+        }
+    }
+}
+
 // One wave per relabelled row.  Each caller column is mapped to its label
 // once (the gather inv[col] is the costly part: random 4-byte reads): rows of
 // at most 64 entries keep the labels in registers and are placed in one pass
@@ -160,6 +218,7 @@ __global__ void __launch_bounds__(256) relabel_rows(const GraphStats* __restrict
     for (int r = 0; r < kColRanges; ++r) bnd[r] = bounds[r];
     for (int64_t L = (int64_t)blockIdx.x * 4 + wave; L < nr; L += (int64_t)gridDim.x * 4) {
         const int64_t o = perm[L], s = rp[o], e = rp[o + 1];
+        if (e - s <= kShortRow || e - s > kBigRow) continue;  // relabel_short_rows / the chunk kernels
         const int64_t dst = rp2[L];
         if (e - s <= 64) {
             const int64_t k = s + lane;
@@ -225,6 +284,143 @@ __global__ void __launch_bounds__(256) relabel_rows(const GraphStats* __restrict
     }
 }
 
+// Chunks per long row (0 for the others); len[n] = 0 closes the scan.
+__global__ void __launch_bounds__(256) long_row_chunks(int64_t n, const GraphStats* __restrict__ st,
+                                                       const int64_t* __restrict__ rp2, long long* __restrict__ cnt) {
+    const int64_t nr = st->n_rows;
+    for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L <= n; L += (int64_t)gridDim.x * 256) {
+        const int64_t len = L < nr ? rp2[L + 1] - rp2[L] : 0;
+        cnt[L] = len > kBigRow ? (len + kRelabelChunk - 1) / kRelabelChunk : 0;
+    }
+}
+
+// Row of global chunk g: the largest L with chunk_off[L] <= g (chunk_off is
+// non-decreasing, chunk_off[L + 1] > g for the owning row).
+__device__ __forceinline__ int64_t chunk_row(const int64_t* __restrict__ chunk_off, int64_t n, int64_t g) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (chunk_off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Phase 1: each chunk maps its columns to labels (parked in tmp at the row's
+// offsets, caller order) and counts them per range.
+__global__ void __launch_bounds__(256) long_row_count(int64_t n, const int64_t* __restrict__ chunk_off,
+                                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                      const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ inv,
+                                                      const int64_t* __restrict__ bounds,
+                                                      const int64_t* __restrict__ rp2, int32_t* __restrict__ tmp,
+                                                      int32_t* __restrict__ ccnt) {
+    __shared__ int hist[kColRanges];
+    __shared__ int64_t row;
+    int64_t bnd[kColRanges];
+#pragma unroll
+    for (int r = 0; r < kColRanges; ++r) bnd[r] = bounds[r];
+    const int64_t C = chunk_off[n];
+    for (int64_t g = blockIdx.x; g < C; g += gridDim.x) {
+        if (threadIdx.x < kColRanges) hist[threadIdx.x] = 0;
+        if (threadIdx.x == 0) row = chunk_row(chunk_off, n, g);
+        __syncthreads();
+        const int64_t L = row, q = g - chunk_off[L];
+        const int64_t o = perm[L];
+        const int64_t s = rp[o] + q * kRelabelChunk, e0 = rp[o + 1];
+        const int64_t k = s + threadIdx.x;
+        if (k < e0 && threadIdx.x < kRelabelChunk) {
+            const int32_t c = inv[col[k]];
+            tmp[rp2[L] + q * kRelabelChunk + threadIdx.x] = c;
+            atomicAdd(&hist[range_of(c, bnd)], 1);  // integer counts: order does not matter
+        }
+        __syncthreads();
+        if (threadIdx.x < kColRanges) ccnt[g * kColRanges + threadIdx.x] = hist[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// Phase 2: one thread per long row turns the chunk counts into each chunk's
+// first position per range within the row (ranges in order, chunks in order).
+__global__ void __launch_bounds__(256) long_row_offsets(int64_t n, const GraphStats* __restrict__ st,
+                                                        const int64_t* __restrict__ chunk_off,
+                                                        const int32_t* __restrict__ ccnt, int32_t* __restrict__ coff) {
+    const int64_t nr = st->n_rows;
+    for (int64_t L = (int64_t)blockIdx.x * 256 + threadIdx.x; L < nr; L += (int64_t)gridDim.x * 256) {
+        const int64_t g0 = chunk_off[L], g1 = chunk_off[L + 1];
+        if (g0 == g1) continue;
+        int tot[kColRanges];
+#pragma unroll
+        for (int r = 0; r < kColRanges; ++r) tot[r] = 0;
+        for (int64_t g = g0; g < g1; ++g)
+#pragma unroll
+            for (int r = 0; r < kColRanges; ++r) tot[r] += ccnt[g * kColRanges + r];
+        int run[kColRanges];
+        int base = 0;
+#pragma unroll
+        for (int r = 0; r < kColRanges; ++r) {
+            run[r] = base;
+            base += tot[r];
+        }
+        for (int64_t g = g0; g < g1; ++g)
+#pragma unroll
+            for (int r = 0; r < kColRanges; ++r) {
+                coff[g * kColRanges + r] = run[r];
+                run[r] += ccnt[g * kColRanges + r];
+            }
+    }
+}
+
+// Phase 3: each chunk places its labels, ranked within the chunk by wave
+// ballots and a prefix over the 4 waves (caller order within a range).
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(256) long_row_place(int64_t n, const int64_t* __restrict__ chunk_off,
+                                                      const int64_t* __restrict__ rp, const float* __restrict__ w,
+                                                      const int32_t* __restrict__ perm,
+                                                      const int64_t* __restrict__ bounds,
+                                                      const int64_t* __restrict__ rp2,
+                                                      const int32_t* __restrict__ tmp,
+                                                      const int32_t* __restrict__ coff, int32_t* __restrict__ col2,
+                                                      float* __restrict__ w2) {
+    __shared__ int wcnt[4][kColRanges];
+    __shared__ int64_t row;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int64_t bnd[kColRanges];
+#pragma unroll
+    for (int r = 0; r < kColRanges; ++r) bnd[r] = bounds[r];
+    const int64_t C = chunk_off[n];
+    for (int64_t g = blockIdx.x; g < C; g += gridDim.x) {
+        if (threadIdx.x == 0) row = chunk_row(chunk_off, n, g);
+        __syncthreads();
+        const int64_t L = row, q = g - chunk_off[L];
+        const int64_t o = perm[L];
+        const int64_t s = rp[o] + q * kRelabelChunk, e0 = rp[o + 1];
+        const int64_t k = s + threadIdx.x;
+        const bool valid = k < e0 && threadIdx.x < kRelabelChunk;
+        int32_t c = 0;
+        int x = -1;
+        if (valid) {
+            c = tmp[rp2[L] + q * kRelabelChunk + threadIdx.x];
+            x = range_of(c, bnd);
+        }
+        uint64_t m[kColRanges];
+#pragma unroll
+        for (int r = 0; r < kColRanges; ++r) {
+            m[r] = __ballot(x == r);
+            if (lane == 0) wcnt[wave][r] = __popcll(m[r]);
+        }
+        __syncthreads();
+        if (valid) {
+            int before = 0;
+            for (int v = 0; v < wave; ++v) before += wcnt[v][x];
+            const int64_t p = rp2[L] + coff[g * kColRanges + x] + before + __popcll(m[x] & lt);
+            col2[p] = c;
+            if (WEIGHTED) w2[p] = w[k];
+        }
+        __syncthreads();
+    }
+}
+
 slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp, const int32_t* col,
                           const float* w, const float* diag_caller, const double* diag64_caller, GraphStats* st,
                           int64_t* bounds, hipStream_t stream) {
@@ -246,6 +442,16 @@ slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp,
     if (s != SLAQ_OK) return s;
     hipLaunchKernelGGL(range_bounds, dim3(1), dim3(64), 0, stream, st, bounds);
     SLAQ_LAUNCHED();
+    int64_t sb = (n + 255) / 256;
+    if (sb > 8192) sb = 8192;
+    if (sb < 1) sb = 1;
+    if (w)
+        hipLaunchKernelGGL(relabel_short_rows<true>, dim3((unsigned)sb), dim3(256), 0, stream, st, rp, col, w, B.perm,
+                           B.inv, bounds, B.row_ptr, B.col, B.w);
+    else
+        hipLaunchKernelGGL(relabel_short_rows<false>, dim3((unsigned)sb), dim3(256), 0, stream, st, rp, col, w, B.perm,
+                           B.inv, bounds, B.row_ptr, B.col, B.w);
+    SLAQ_LAUNCHED();
     int64_t rb = (n + 3) / 4;
     if (rb > 8192) rb = 8192;
     if (rb < 1) rb = 1;
@@ -255,6 +461,24 @@ slaq_status relabel_build(const RelabelBuffers& B, int64_t n, const int64_t* rp,
     else
         hipLaunchKernelGGL(relabel_rows<false>, dim3((unsigned)rb), dim3(256), 0, stream, st, rp, col, w, B.perm,
                            B.inv, bounds, B.row_ptr, B.col, B.w, B.tmp);
+    SLAQ_LAUNCHED();
+    // long rows in chunks (B.len is free again once the row offsets exist)
+    hipLaunchKernelGGL(long_row_chunks, dim3(lb), dim3(256), 0, stream, n, st, B.row_ptr, B.len);
+    SLAQ_LAUNCHED();
+    s = exclusive_scan(B.len, n + 1, B.chunk_off, B.bsum, nullptr, nullptr, stream);
+    if (s != SLAQ_OK) return s;
+    const int cb = 8192;
+    hipLaunchKernelGGL(long_row_count, dim3(cb), dim3(256), 0, stream, n, B.chunk_off, rp, col, B.perm, B.inv, bounds,
+                       B.row_ptr, B.tmp, B.ccnt);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(long_row_offsets, dim3(lb), dim3(256), 0, stream, n, st, B.chunk_off, B.ccnt, B.coff);
+    SLAQ_LAUNCHED();
+    if (w)
+        hipLaunchKernelGGL(long_row_place<true>, dim3(cb), dim3(256), 0, stream, n, B.chunk_off, rp, w, B.perm, bounds,
+                           B.row_ptr, B.tmp, B.coff, B.col, B.w);
+    else
+        hipLaunchKernelGGL(long_row_place<false>, dim3(cb), dim3(256), 0, stream, n, B.chunk_off, rp, w, B.perm,
+                           bounds, B.row_ptr, B.tmp, B.coff, B.col, B.w);
     SLAQ_LAUNCHED();
     return SLAQ_OK;
 }

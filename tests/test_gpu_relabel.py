@@ -156,6 +156,23 @@ def test_relabelled_weighted():
         assert_signature_parity(gpu, ora, csr.n, f"relabel weighted lap={lap}")
 
 
+@pytest.mark.parametrize("lap", [S.SLAQ_LAP_NORMALIZED, S.SLAQ_LAP_COMBINATORIAL])
+def test_relabelled_weighted_hub_rows(lap):
+    # rows of more than 1024 entries take the chunked relabelling path; their
+    # weights must travel with their columns
+    header(f"relabel weighted hubs lap={lap}")
+    csr = with_isolated(inputs.chung_lu(6000, 60000, 2.1, seed=13), 200, seed=4)
+    assert np.diff(csr.row_ptr).max() > 1024
+    r = np.repeat(np.arange(csr.n), np.diff(csr.row_ptr))
+    c = csr.col_idx.astype(np.int64)
+    lo, hi = np.minimum(r, c), np.maximum(r, c)
+    w = (0.5 + ((lo * 977 + hi * 131) % 23) / 11.0).astype(np.float32)
+    gpu = gpu_run(csr, 16, 12, 21, T256, laplacian=lap, weights=w, relabel=True)
+    ora = oracle_run(csr, 16, 12, 21, T256, laplacian=lap, weights=w.astype(np.float64))
+    np.testing.assert_allclose(gpu["alpha"][:, :6], ora["alpha"][:, :6], rtol=1e-5)
+    assert_signature_parity(gpu, ora, csr.n, f"relabel weighted hubs lap={lap}")
+
+
 @pytest.mark.parametrize("heavy_min,piece", [(128, 64), (256, 256), (128, 1024)])
 def test_relabelled_schedules(heavy_min, piece):
     header(f"relabel schedule {heavy_min}/{piece}")
