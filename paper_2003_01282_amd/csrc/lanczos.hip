@@ -644,8 +644,8 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     L.Gu = L.F < kQuadsPerTile ? L.F : kQuadsPerTile;
     L.Ku = 64 / L.Gu;
     L.ntiles_u = (L.F + kQuadsPerTile - 1) / kQuadsPerTile;
-    // rows per wave window: up to 64, fewer on small graphs so that the
-    // windows still cover every resident wave (never fewer than K)
+    // rows per wave window: up to kRowsPerWindow, fewer on small graphs so
+    // that the windows still cover every resident wave (never fewer than K)
     const int64_t target_waves = 8192;
     int64_t rw = (g->n + target_waves - 1) / target_waves;
     if (rw > kRowsPerWindow) rw = kRowsPerWindow;
