@@ -42,7 +42,9 @@ def oracle_run(csr, nv, m, seed, t, laplacian=O.NORMALIZED, weights=None):
 
 
 def assert_signature_parity(gpu, ora, n, label=""):
-    rel = np.abs(gpu["heat"] - ora["heat"]) / np.abs(ora["heat"])
+    # identical entries (a heat trace that underflowed to 0 on both sides) count as exact
+    same = gpu["heat"] == ora["heat"]
+    rel = np.where(same, 0.0, np.abs(gpu["heat"] - ora["heat"]) / np.where(same, 1.0, np.abs(ora["heat"])))
     assert rel.max() <= TOL_HEAT_REL, f"{label} heat rel {rel.max():.3e}"
     dw = np.abs(gpu["wave"] - ora["wave"]).max() / n
     assert dw <= TOL_WAVE_ABS_N, f"{label} wave |d|/n {dw:.3e}"
