@@ -208,6 +208,30 @@ def test_quadrature_alone_on_oracle_nodes():
     assert abs(H - ora["vnge"]) <= 1e-13 * abs(ora["vnge"])
 
 
+def test_maximum_probe_and_step_counts():
+    # nv = SLAQ_MAX_PROBES, m = SLAQ_MAX_STEPS, with isolated nodes; FP32
+    # vectors in caller order, FP64 vectors relabelled.  Without
+    # reorthogonalisation the coefficients after the first Ritz values
+    # converge carry amplified rounding (an FP32 emulation of this recurrence
+    # on the CPU differs from the FP64 one by 1e-5 at step 16 and by 35% at
+    # step 24), while the Gauss rules they define stay equivalent: the
+    # coefficients are compared over the first 12 steps, the signatures in full.
+    nv, m = S.SLAQ_MAX_PROBES, S.SLAQ_MAX_STEPS
+    header(f"Chung-Lu n=1000 nv={nv} m={m}")
+    csr = inputs.chung_lu(1000, 4000, 2.4, seed=64)
+    assert np.any(np.diff(csr.row_ptr) == 0)
+    ora = oracle_run(csr, nv, m, 7, T256)
+    for prec, relabel, tol in ((S.SLAQ_PREC_FP32, False, 1e-4), (S.SLAQ_PREC_FP64, True, 1e-9)):
+        print(f"precision {prec} relabel {relabel}", flush=True)
+        gpu = gpu_run(csr, nv, m, 7, T256, relabel=relabel, precision=prec)
+        assert np.array_equal(gpu["steps"], ora["steps"])
+        np.testing.assert_allclose(gpu["alpha"][:, :12], ora["alpha"][:, :12], rtol=tol, atol=tol * 1e-2)
+        np.testing.assert_allclose(gpu["beta"][:, :12], ora["beta"][:, :12], rtol=tol, atol=tol * 1e-2)
+        rh, rw = assert_signature_parity(gpu, ora, csr.n, f"max sizes prec={prec}")
+        print(f"heat rel {rh:.2e} wave |d|/n {rw:.2e}", flush=True)
+        np.testing.assert_allclose(gpu["tau2"].sum(axis=1), 1.0, atol=1e-9)
+
+
 def test_deterministic_bitwise():
     header("determinism")
     csr = inputs.chung_lu(10_000, 50_000, 2.5, seed=11)
