@@ -10,8 +10,11 @@ Default workload: R-MAT scale 22 (n = 4,194,304, edge factor 16,
 a=0.57 b=c=0.19, ~1.28e8 stored nonzeros), nv = 100 probes, m = 15 steps.
 `value` is nnz * nv * m per second of the whole step.  The roofline entry
 covers the SpMM stage kernels, timed live with HIP events on the launch stream.
+Other workloads: R-MAT scale 26 (~2.1e9 stored nonzeros, generated on the
+device), Chung-Lu n = 1e4, the batched small graphs and the learned closure;
+--permute renames the nodes of a host-generated graph at random first.
 
-    python bench.py [--steps K] [--warmup W] [--workload rmat22|chung_lu]
+    python bench.py [--steps K] [--warmup W] [--workload rmat22|rmat26|chung_lu|batched|closure] [--permute]
 """
 import argparse
 import json
@@ -27,6 +30,7 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     # name: (generator kwargs, nv, m)
     "rmat22": (dict(kind="rmat", scale=22, seed=1), 100, 15),
+    "rmat26": (dict(kind="rmat_device", scale=26, seed=1), 100, 15),
     "chung_lu": (dict(kind="chung_lu", n=10_000, pairs=50_000, seed=1), 10, 15),
     "batched": (dict(kind="mix", count=5000, seed=1), 20, 10),
     "closure": (dict(kind="closure", train=20000, test=2000, n_lo=1000, n_hi=100000, seed=1), 20, 5),
@@ -62,12 +66,12 @@ def update_algorithmic_bytes(n, n_act, nv):
 TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "spmm_rmat22_traffic.json")
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, permuted):
     """HBM bytes per SpMM-stage launch from the committed FETCH_SIZE /
     WRITE_SIZE record, or None when there is none for this workload or the
     kernel sources changed since it was taken."""
     from paper_2003_01282_amd.profsum import kernel_sources_digest
-    if workload != "rmat22" or not os.path.exists(TRAFFIC_RECORD):
+    if workload != "rmat22" or permuted or not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = json.load(open(TRAFFIC_RECORD))
     if rec.get("digest") != kernel_sources_digest():
@@ -296,12 +300,12 @@ def bench_closure(args):
 
 
 def line_probe():
-    """Random 128-B-line read rate for working sets of 2 MiB to 4 GiB (the
+    """Random 128-B-line read rate for working sets of 2 MiB to 16 GiB (the
     ceiling of gathers that miss L2), from libslaq_probe.so."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2003_01282_amd",
                                    "libslaq_probe.so"))
-    mib = [2, 8, 16, 32, 64, 128, 256, 512, 1024, 4096]
+    mib = [2, 8, 16, 32, 64, 128, 256, 512, 1024, 4096, 8192, 16384]
     sizes = (ctypes.c_size_t * len(mib))(*[x << 20 for x in mib])
     out = (ctypes.c_double * len(mib))()
     rc = lib.slaq_line_probe(sizes, len(mib), out)
@@ -327,14 +331,16 @@ def main():
     ap.add_argument("--closure-epochs", type=int, default=12)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (calibrates hardware byte counters)")
+    ap.add_argument("--permute", action="store_true",
+                    help="rename the nodes of a host-generated graph by a seeded random permutation first")
     ap.add_argument("--line-probe", action="store_true",
                     help="only measure random 128-byte-line read throughput against working-set size")
     args = ap.parse_args()
     if args.line_probe:
         return line_probe()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(probe sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the probe sharding across GPUs is a design, not built",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched":
@@ -349,12 +355,22 @@ def main():
     spec, nv, m = WORKLOADS[args.workload]
     log(f"generating {args.workload} {spec}")
     t0 = time.perf_counter()
-    csr = make_graph(spec)
-    log(f"graph n={csr.n} nnz={csr.nnz} in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    rp = torch.from_numpy(csr.row_ptr).to(dev)
-    ci = torch.from_numpy(csr.col_idx).to(dev)
+    if spec["kind"] == "rmat_device":
+        if args.permute:
+            raise SystemExit("--permute applies to host-generated graphs")
+        csr = None
+        rp, ci = inputs.rmat_device(spec["scale"], seed=spec["seed"], device=dev)
+        n, nnz = rp.numel() - 1, ci.numel()
+    else:
+        csr = make_graph(spec)
+        if args.permute:
+            csr = inputs.permute(csr, seed=1)
+        n, nnz = csr.n, csr.nnz
+        rp = torch.from_numpy(csr.row_ptr).to(dev)
+        ci = torch.from_numpy(csr.col_idx).to(dev)
+    log(f"graph n={n} nnz={nnz}{' (permuted)' if args.permute else ''} in {time.perf_counter() - t0:.1f} s")
     tgrid = torch.from_numpy(inputs.t_grid(256)).to(dev)
     nt = tgrid.numel()
 
@@ -396,8 +412,8 @@ def main():
             g.set_tile(args.tile)
         S.lanczos(g, nv, m, args.seed, workspace=ws, out=(alpha, beta, steps))
         S.ritz(alpha, beta, steps, out=(theta, tau2))
-        S.signature(theta, tau2, csr.n, tgrid, S.SLAQ_SIG_HEAT, out=heat)
-        S.signature(theta, tau2, csr.n, tgrid, S.SLAQ_SIG_WAVE, out=wave)
+        S.signature(theta, tau2, n, tgrid, S.SLAQ_SIG_HEAT, out=heat)
+        S.signature(theta, tau2, n, tgrid, S.SLAQ_SIG_WAVE, out=wave)
         S.vnge(g, theta, tau2, out=H)
         graphs[0] = g  # keep the handle alive until the next step
 
@@ -426,11 +442,12 @@ def main():
     # SpMM stage = pieces + light rows + heavy-row epilogue, per Lanczos step
     # (with several probe tiles each kernel runs once per tile)
     spmm_ms = sum(stages[k]["ms_per_step"] for k in ("spmm_pieces", "spmm_rows", "spmm_heavy")) / m
-    n_act = csr.n - int(np.count_nonzero(np.diff(csr.row_ptr) == 0))
-    spmm_bytes = spmm_algorithmic_bytes(csr.n, n_act, csr.nnz, nv)
+    n_act = n - graphs[0].info()["n_isolated"]
+    spmm_bytes = spmm_algorithmic_bytes(n, n_act, nnz, nv)
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
     upd_ms = stages["update"]["avg_ms"]
-    upd_gbs = update_algorithmic_bytes(csr.n, n_act, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
+    upd_gbs = update_algorithmic_bytes(n, n_act, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
+    traffic = measured_traffic(args.workload, args.permute)
 
     # the variance-reduced estimate (control variates tr L, tr L^2; fitted
     # coefficients), timed once after the timed region: it is not part of the
@@ -445,8 +462,8 @@ def main():
         ev[0].record()
         S.graph_traces(graphs[0], out=tr)
         ev[1].record()
-        S.signature_cv(theta, tau2, csr.n, tr, tgrid, S.SLAQ_SIG_HEAT, S.SLAQ_CV_FITTED, out=heat_cv)
-        S.signature_cv(theta, tau2, csr.n, tr, tgrid, S.SLAQ_SIG_WAVE, S.SLAQ_CV_FITTED, out=wave_cv)
+        S.signature_cv(theta, tau2, n, tr, tgrid, S.SLAQ_SIG_HEAT, S.SLAQ_CV_FITTED, out=heat_cv)
+        S.signature_cv(theta, tau2, n, tr, tgrid, S.SLAQ_SIG_WAVE, S.SLAQ_CV_FITTED, out=wave_cv)
         S.vnge_cv(graphs[0], theta, tau2, tr, S.SLAQ_CV_FITTED, out=H_cv)
         ev[2].record()
         torch.cuda.synchronize()
@@ -455,10 +472,12 @@ def main():
         log(f"variance reduction: {vr}")
 
     h = heat.cpu().numpy()
-    sanity = bool(np.all(np.isfinite(h)) and np.all(np.diff(h) <= 1e-9 * csr.n) and 0 < h[-1] < csr.n)
+    sanity = bool(np.all(np.isfinite(h)) and np.all(np.diff(h) <= 1e-9 * n) and 0 < h[-1] < n)
 
+    # the oracle needs a host copy of the graph: timed for host-generated
+    # workloads only (a scale-26 graph takes ~25 GB as a scipy matrix)
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and csr is not None:
         log("cpu baseline (oracle on a probe subset)")
         cpu = cpu_baseline(csr, nv, m, args.seed)
         cpu["cores"] = 1
@@ -471,7 +490,7 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": csr.nnz * nv * m / (ms_per_step * 1e-3),
+        "value": nnz * nv * m / (ms_per_step * 1e-3),
         "unit": "nnz*probes*steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -482,14 +501,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}_slq", "n": csr.n, "nnz": csr.nnz, "nv": nv, "m": m,
+        "config": {"workload": f"{args.workload}_slq", "n": n, "nnz": nnz, "nv": nv, "m": m,
                    "nt": nt, "outputs": ["heat", "wave", "vnge"], "laplacian": "normalized",
-                   "generator": spec, "n_nonisolated": n_act, "schedule": graphs[0].schedule(),
+                   "generator": spec, "permuted": args.permute, "n_nonisolated": n_act,
+                   "relabeled": graphs[0].relabeled(), "schedule": graphs[0].schedule(),
                    "tile_quads": args.tile},
         "roofline": {"bound": "hbm", "kernel": "spmm_pieces+spmm_rows+spmm_heavy", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(args.workload),
-                     "bytes_per_launch": spmm_bytes, "avg_launch_ms": spmm_ms},
+                     "traffic": traffic, "bytes_per_launch": spmm_bytes, "avg_launch_ms": spmm_ms,
+                     "traffic_gbs": traffic / (spmm_ms * 1e-3) / 1e9 if traffic else None,
+                     "amplification": traffic / spmm_bytes if traffic else None},
         "spmm_hbm_gbs": achieved,
         "update_gbs": upd_gbs,
         "stages": stages,

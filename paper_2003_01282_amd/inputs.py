@@ -66,6 +66,24 @@ def _rng(seed, *stream):
     return np.random.default_rng(np.random.SeedSequence([int(seed), *[int(s) for s in stream]]))
 
 
+def permute(csr, seed=0, return_perm=False):
+    """The same graph under a seeded uniformly random renaming of its nodes
+    (node i becomes p[i]): the stress input for layouts that lean on the
+    generator's id order.  With return_perm, also p."""
+    p = _rng(seed, 9).permutation(csr.n).astype(np.int64)
+    rows = p[np.repeat(np.arange(csr.n, dtype=np.int64), np.diff(csr.row_ptr))]
+    key = rows * csr.n + p[csr.col_idx]
+    del rows
+    key.sort()
+    r = key // csr.n
+    cols = (key - r * csr.n).astype(np.int32)
+    del key
+    row_ptr = np.zeros(csr.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=csr.n), out=row_ptr[1:])
+    out = CSR(n=csr.n, row_ptr=row_ptr, col_idx=cols)
+    return (out, p) if return_perm else out
+
+
 def chung_lu(n, n_pairs, gamma=2.5, seed=0):
     """Chung-Lu power-law graph: node i has weight (i+1)^(-1/(gamma-1)); each of
     n_pairs endpoint pairs draws both ends independently with probability

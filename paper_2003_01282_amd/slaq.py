@@ -179,6 +179,13 @@ class Graph:
                                          ctypes.byref(npc)))
         return {"heavy_min": hm.value, "piece": pc.value, "n_heavy": nh.value, "n_pieces": npc.value}
 
+    def relabeled(self):
+        """Whether the build relabelled the nodes (slaq_graph_internal with
+        only the flag asked for: nothing is copied)."""
+        rel = _int()
+        _check(lib().slaq_graph_internal(self.handle, ctypes.byref(rel), None, None, None, None))
+        return bool(rel.value)
+
     def internal(self):
         """slaq_graph_internal -> dict(relabeled, n_rows, perm, row_ptr, col_idx)
         (device tensors: label -> caller id, and the internal CSR)."""
