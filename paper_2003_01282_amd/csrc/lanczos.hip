@@ -21,6 +21,14 @@
 // spectrum within a few steps).  A "quad" is 16 bytes of a probe row: 4 floats
 // or 2 doubles; a lane holds one quad.
 //
+// Block layout: a probe row of F quads is split into a main part of
+// Fm = 8 floor(F / 8) quads (whole 128-byte lines, rows line-aligned) and a
+// tail of Ft = F - Fm quads kept in a region of its own.  A row gather then
+// touches Fm / 8 lines plus one 16 Ft-byte tail slot, where tails of eight or
+// more rows share a line and stay in cache far longer; an unsplit 400-byte
+// row (nv = 100) straddles four lines at any alignment.  Each lane serves one
+// quad and so reads one region with one stride (VecMap::lane).
+//
 // Normalized Laplacian: the probe blocks are stored in the scaled basis
 // X_j = D^-1/2 R_j (per row, with the same D^-1/2 the kernels read), so the
 // SpMM sums plain neighbour rows, (A X_j)_i, with no per-nonzero scale; the
@@ -52,6 +60,23 @@ template <typename V>
 struct alignas(16) Quad {
     static constexpr int E = 16 / sizeof(V);
     V v[E];
+};
+
+// Split row layout of a probe block (see the top of this file): quad q < Fm
+// of row i at quad index i Fm + q, quad q >= Fm at tail + i Ft + (q - Fm).
+struct VecMap {
+    int Fm, Ft;
+    int64_t tail;
+    // quad index of (row i, this lane's quad) = off + i * stride
+    __device__ __forceinline__ void lane(int quad, int64_t& off, int& stride) const {
+        if (quad < Fm) {
+            off = quad;
+            stride = Fm;
+        } else {
+            off = tail + (quad - Fm);
+            stride = Ft;
+        }
+    }
 };
 
 // Per-probe FP64 recurrence state (workspace).
@@ -170,7 +195,7 @@ __global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double 
 // One quad per thread, rows strided.
 template <typename V>
 __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__ st, int laplacian, int nv, int F,
-                                                  int rows_per_sweep, uint64_t seed,
+                                                  VecMap vm, int rows_per_sweep, uint64_t seed,
                                                   const V* __restrict__ diag,
                                                   const int32_t* __restrict__ perm, Quad<V>* __restrict__ R) {
     constexpr int E = Quad<V>::E;
@@ -178,6 +203,9 @@ __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__
     const int quad = tid % F;
     const int64_t row0 = tid / F;
     if (row0 >= rows_per_sweep) return;
+    int64_t mo;
+    int ms;
+    vm.lane(quad, mo, ms);
     const int64_t n = st->n_rows;
     const int p0 = E * quad;
     const uint64_t word = (uint64_t)(p0 >> 6);
@@ -193,7 +221,7 @@ __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__
             const V sgn = ((z >> (bit0 + c)) & 1ull) ? -one : one;
             v.v[c] = (p0 + c < nv) ? sgn : V(0);
         }
-        R[i * F + quad] = v;
+        R[mo + i * ms] = v;
     }
 }
 
@@ -204,8 +232,8 @@ __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__
 template <int MODE, bool WEIGHTED, typename V>
 __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t k1, int gbase, int gl, int G,
                                               const int32_t* __restrict__ col, const float* __restrict__ w,
-                                              const V* __restrict__ diag, const Quad<V>* __restrict__ R,
-                                              int F, int quad, bool lane_ok) {
+                                              const V* __restrict__ diag, const Quad<V>* __restrict__ Rl,
+                                              int ms, bool lane_ok) {
     for (int64_t kb = k0; kb < k1; kb += G) {
         const int cnt = (int)((k1 - kb) < G ? (k1 - kb) : G);
         int32_t cl = 0;
@@ -225,14 +253,14 @@ __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t 
                 s[v] = __shfl(sl, gbase + u + v);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? R[(int64_t)c[v] * F + quad] : qzero<V>();
+            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? Rl[(int64_t)c[v] * ms] : qzero<V>();
 #pragma unroll
             for (int v = 0; v < 4; ++v) qfma(s[v], x[v], acc);
         }
         for (; u < cnt; ++u) {
             const int32_t c = __shfl(cl, gbase + u);
             const V s = __shfl(sl, gbase + u);
-            if (lane_ok) qfma(s, R[(int64_t)c * F + quad], acc);
+            if (lane_ok) qfma(s, Rl[(int64_t)c * ms], acc);
         }
     }
 }
@@ -250,7 +278,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                                                    const float* __restrict__ w,
                                                    const V* __restrict__ diag,
                                                    const Quad<V>* __restrict__ R,
-                                                   Quad<V>* __restrict__ P, int F, int G, int K, int piece,
+                                                   Quad<V>* __restrict__ P, int F, VecMap vm, int G, int K, int piece,
                                                    int tile0, int TQ) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
@@ -260,6 +288,10 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
     const bool lane_ok = in_group && quad < F;
     const int64_t nh = st->n_heavy;
     if (nh == 0) return;
+    int64_t mo;
+    int ms;
+    vm.lane(quad, mo, ms);
+    const Quad<V>* __restrict__ Rl = R + mo;
     const int x = blockIdx.x % kColRanges;
     const int64_t waves_x = (int64_t)(gridDim.x / kColRanges) * 4;
     const int64_t wi = (int64_t)(blockIdx.x / kColRanges) * 4 + wave;
@@ -310,7 +342,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                 }
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v)
-                    xv[v] = (lane_ok && s[v] != V(0)) ? R[(int64_t)c[v] * F + quad] : qzero<V>();
+                    xv[v] = (lane_ok && s[v] != V(0)) ? Rl[(int64_t)c[v] * ms] : qzero<V>();
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v) qfma(s[v], xv[v], acc);
             }
@@ -319,7 +351,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                 const int src = u < 64 ? u : 63;
                 const int32_t c = __shfl(cl, src);
                 const V s = __shfl(sl, src);
-                if (lane_ok && u < cnt) qfma(s, R[(int64_t)c * F + quad], acc);
+                if (lane_ok && u < cnt) qfma(s, Rl[(int64_t)c * ms], acc);
             }
         }
         // fixed-order tree over the K groups (lane + st*G)
@@ -341,15 +373,16 @@ template <int MODE, typename V>
 __device__ __forceinline__ void row_epilogue(int64_t i, const Quad<V>& acc, const V* __restrict__ diag,
                                              const Quad<V>* __restrict__ R, const Quad<V>* __restrict__ Rp,
                                              Quad<V>* __restrict__ W, const Quad<V>& sg, const Quad<V>& tp,
-                                             int has_prev, int F, int quad, double (&s1)[Quad<V>::E]) {
+                                             int has_prev, int64_t mo, int ms, double (&s1)[Quad<V>::E]) {
     constexpr int E = Quad<V>::E;
-    const Quad<V> ri = R[i * F + quad];
+    const int64_t at = mo + i * ms;
+    const Quad<V> ri = R[at];
     const V di = diag[i];
     const double dd = (double)di, d2 = dd * dd;
     // per-row arithmetic in FP64, one rounding to the storage precision (the
     // scale dinv_i^2 stays exact, so the scaled operator stays symmetric)
     Quad<V> rq = qzero<V>();
-    if (has_prev) rq = Rp[i * F + quad];
+    if (has_prev) rq = Rp[at];
     Quad<V> wi;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -359,7 +392,7 @@ __device__ __forceinline__ void row_epilogue(int64_t i, const Quad<V>& acc, cons
         if (has_prev) wv = fma(-(double)tp.v[e], (double)rq.v[e], wv);
         wi.v[e] = (V)wv;
     }
-    W[i * F + quad] = wi;
+    W[at] = wi;
     // FP32: products of two floats are exact in double
     if (MODE == SLAQ_LAP_NORMALIZED) {
         const double wgt = di != V(0) ? 1.0 / d2 : 0.0;  // zero weight sum: no data
@@ -382,7 +415,7 @@ __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__
                                                   const Quad<V>* __restrict__ R, const Quad<V>* __restrict__ Rp,
                                                   Quad<V>* __restrict__ W, const V* __restrict__ coef,
                                                   int has_prev, double* __restrict__ part, int nb, int col0, int F,
-                                                  int G, int K, int ld, int tile0, int TQ) {
+                                                  VecMap vm, int G, int K, int ld, int tile0, int TQ) {
     constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
@@ -391,6 +424,9 @@ __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
     const int64_t nh = st->n_heavy;
+    int64_t mo;
+    int ms;
+    vm.lane(quad, mo, ms);
     double s1[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) s1[e] = 0.0;
@@ -423,7 +459,7 @@ __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__
             if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) qadd(acc, o);
         }
         if (gi == 0 && lane_ok)
-            row_epilogue<MODE, V>((int64_t)hrow[h], acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
+            row_epilogue<MODE, V>((int64_t)hrow[h], acc, diag, R, Rp, W, sg, tp, has_prev, mo, ms, s1);
     }
     block_reduce_store<E>(s1, part, nb, F, G, K, ld, tile, TQ, col0);
 }
@@ -440,8 +476,8 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
                                                  const Quad<V>* __restrict__ R,
                                                  const Quad<V>* __restrict__ Rp,
                                                  Quad<V>* __restrict__ W, const V* __restrict__ coef,
-                                                 int has_prev, double* __restrict__ part, int nb, int F, int G,
-                                                 int K, int ld, int rw, int tile0, int TQ) {
+                                                 int has_prev, double* __restrict__ part, int nb, int F, VecMap vm,
+                                                 int G, int K, int ld, int rw, int tile0, int TQ) {
     constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
@@ -450,6 +486,9 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
     const int quad = tile * TQ + gl;
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
+    int64_t mo;
+    int ms;
+    vm.lane(quad, mo, ms);
 
     double s1[E];
 #pragma unroll
@@ -476,9 +515,9 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
             if (!in_group || t >= rw || i >= n || e == s) continue;  // isolated: nothing stored
             if (e - s >= heavy_min) continue;  // heavy rows: spmm_heavy
             Quad<V> acc = qzero<V>();
-            group_segment<MODE, WEIGHTED, V>(acc, s, e, gbase, gl, G, col, w, diag, R, F, quad, lane_ok);
+            group_segment<MODE, WEIGHTED, V>(acc, s, e, gbase, gl, G, col, w, diag, R + mo, ms, lane_ok);
             if (!lane_ok) continue;
-            row_epilogue<MODE, V>(i, acc, diag, R, Rp, W, sg, tp, has_prev, F, quad, s1);
+            row_epilogue<MODE, V>(i, acc, diag, R, Rp, W, sg, tp, has_prev, mo, ms, s1);
         }
     }
     block_reduce_store<E>(s1, part, nb, F, G, K, ld, tile, TQ);
@@ -493,7 +532,7 @@ __global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st,
                                               const Quad<V>* __restrict__ W, const Quad<V>* __restrict__ R,
                                               const V* __restrict__ coef, int store,
                                               Quad<V>* __restrict__ Rn, double* __restrict__ part, int nb,
-                                              int F, int G, int K, int ld, int rw, int tile0, int TQ) {
+                                              int F, VecMap vm, int G, int K, int ld, int rw, int tile0, int TQ) {
     constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
@@ -501,6 +540,9 @@ __global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st,
     const int quad = tile * TQ + gl;
     const bool in_group = gi < K;
     const bool lane_ok = in_group && quad < F;
+    int64_t mo;
+    int ms;
+    vm.lane(quad, mo, ms);
     double s2[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) s2[e] = 0.0;
@@ -518,12 +560,13 @@ __global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st,
             const V d = __shfl(d_l, t < 64 ? t : 63);
             const int64_t i = r0 + t;
             if (!lane_ok || t >= rw || i >= n || d == V(0)) continue;
-            const Quad<V> wv = W[i * F + quad];
-            const Quad<V> rv = R[i * F + quad];
+            const int64_t at = mo + i * ms;
+            const Quad<V> wv = W[at];
+            const Quad<V> rv = R[at];
             Quad<V> r;
 #pragma unroll
             for (int e = 0; e < E; ++e) r.v[e] = vfma(-a.v[e], rv.v[e], wv.v[e]);
-            if (store) Rn[i * F + quad] = r;
+            if (store) Rn[at] = r;
             // normalized: ||R_{j+1}||^2 = sum_i X_{j+1,i}^2 / dinv_i^2
             const double wgt = laplacian == SLAQ_LAP_NORMALIZED ? 1.0 / ((double)d * (double)d) : 1.0;
 #pragma unroll
@@ -606,6 +649,7 @@ __global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ par
 // ------------------------------------------------------------ layout ------
 struct Layout {
     int ld, F, G, K, ntiles, TQ, Gu, Ku, ntiles_u, nb_rows, nb_upd, piece_blocks, rw, nb_heavy;
+    VecMap vm;
     int64_t max_pieces;
     size_t off_r[3], off_p, off_part1, off_part2, off_ps, off_coef, total;
 };
@@ -670,7 +714,12 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     int64_t pb = (L.max_pieces + 3) / 4;
     pb = pb < kPieceBlocks ? (pb > 0 ? pb : 1) : kPieceBlocks;
     L.piece_blocks = (int)((pb + kColRanges - 1) / kColRanges * kColRanges);  // a multiple of the ranges
-    const size_t vec = align_up((size_t)g->n * L.ld * sizeof(V), 256);
+    // split rows: main part of whole 128-byte lines, tail region after it
+    L.vm.Fm = L.F / 8 * 8;
+    L.vm.Ft = L.F - L.vm.Fm;
+    const size_t main_bytes = align_up((size_t)g->n * L.vm.Fm * 16, 256);
+    L.vm.tail = (int64_t)(main_bytes / 16);
+    const size_t vec = main_bytes + align_up((size_t)g->n * L.vm.Ft * 16, 256);
     size_t off = 0;
     for (int b = 0; b < 3; ++b) {
         L.off_r[b] = off;
@@ -743,8 +792,8 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
     SLAQ_LAUNCHED();
     int rps = 0;
     const int sgrid = sweep_grid(g->n, L.F, &rps);
-    hipLaunchKernelGGL(probe_init<V>, dim3(sgrid), dim3(256), 0, st, g->stats, mode, nv, L.F, rps, seed, diag, g->perm,
-                       Rb[0]);
+    hipLaunchKernelGGL(probe_init<V>, dim3(sgrid), dim3(256), 0, st, g->stats, mode, nv, L.F, L.vm, rps, seed, diag,
+                       g->perm, Rb[0]);
     SLAQ_LAUNCHED();
 
     int cur = 0, prev = 1;
@@ -758,24 +807,26 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
                 SLAQ_TIMED("spmm_pieces", st,
                            SLAQ_DISPATCH(mode, weighted, spmm_pieces, dim3(L.piece_blocks, 1), dim3(256), 0, st,
                                          g->stats, g->segk, g->segoff, cap, g->col_idx, g->weights, diag, Rb[cur], P,
-                                         L.F, L.G, L.K, g->piece, tile, L.TQ));
+                                         L.F, L.vm, L.G, L.K, g->piece, tile, L.TQ));
                 SLAQ_LAUNCHED();
             }
             SLAQ_TIMED("spmm_rows", st,
                        SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st, g->stats,
                                      g->row_ptr, g->col_idx, g->weights, diag, g->heavy_min, Rb[cur], Rb[prev],
-                                     Rb[wbuf], coef, hp, part1, nbp, L.F, L.G, L.K, L.ld, L.rw, tile, L.TQ));
+                                     Rb[wbuf], coef, hp, part1, nbp, L.F, L.vm, L.G, L.K, L.ld, L.rw, tile, L.TQ));
             SLAQ_LAUNCHED();
             {  // always launched: its blocks write their (zero) dot partials even without heavy rows
                 SLAQ_TIMED("spmm_heavy", st, {
                     if (mode == SLAQ_LAP_NORMALIZED)
                         hipLaunchKernelGGL((spmm_heavy<SLAQ_LAP_NORMALIZED, V>), dim3(L.nb_heavy, 1), dim3(256), 0,
                                            st, g->stats, g->hrow, g->segoff, cap, P, diag, Rb[cur], Rb[prev],
-                                           Rb[wbuf], coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
+                                           Rb[wbuf], coef, hp, part1, nbp, L.nb_rows, L.F, L.vm, L.G, L.K, L.ld, tile,
+                                           L.TQ);
                     else
                         hipLaunchKernelGGL((spmm_heavy<SLAQ_LAP_COMBINATORIAL, V>), dim3(L.nb_heavy, 1), dim3(256), 0,
                                            st, g->stats, g->hrow, g->segoff, cap, P, diag, Rb[cur], Rb[prev],
-                                           Rb[wbuf], coef, hp, part1, nbp, L.nb_rows, L.F, L.G, L.K, L.ld, tile, L.TQ);
+                                           Rb[wbuf], coef, hp, part1, nbp, L.nb_rows, L.F, L.vm, L.G, L.K, L.ld, tile,
+                                           L.TQ);
                 });
                 SLAQ_LAUNCHED();
             }
@@ -787,7 +838,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
         SLAQ_TIMED("update", st,
                    hipLaunchKernelGGL(update<V>, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->stats,
                                       mode, diag, Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F,
-                                      L.Gu, L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
+                                      L.vm, L.Gu, L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
                    hipLaunchKernelGGL(finalize_b<V>, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,
