@@ -66,12 +66,14 @@ def update_algorithmic_bytes(n, n_act, nv):
 TRAFFIC_RECORD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "spmm_rmat22_traffic.json")
 
 
-def measured_traffic(workload, permuted):
+def measured_traffic(args):
     """HBM bytes per SpMM-stage launch from the committed FETCH_SIZE /
-    WRITE_SIZE record, or None when there is none for this workload or the
+    WRITE_SIZE record, or None when there is none for this workload and
+    launch configuration (default schedule and tile, caller order) or the
     kernel sources changed since it was taken."""
     from paper_2003_01282_amd.profsum import kernel_sources_digest
-    if workload != "rmat22" or permuted or not os.path.exists(TRAFFIC_RECORD):
+    default = not (args.permute or args.tile or args.heavy_min or args.piece)
+    if args.workload != "rmat22" or not default or not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = json.load(open(TRAFFIC_RECORD))
     if rec.get("digest") != kernel_sources_digest():
@@ -447,7 +449,7 @@ def main():
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
     upd_ms = stages["update"]["avg_ms"]
     upd_gbs = update_algorithmic_bytes(n, n_act, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
-    traffic = measured_traffic(args.workload, args.permute)
+    traffic = measured_traffic(args)
 
     # the variance-reduced estimate (control variates tr L, tr L^2; fitted
     # coefficients), timed once after the timed region: it is not part of the
