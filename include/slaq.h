@@ -255,16 +255,20 @@ slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, i
  * node_off_dev / row_ptr / col_idx are the device arrays, which must stay
  * valid until slaq_batch_destroy.  Graphs are bucketed by node count
  * (<= 64, 128, 256, ...); bucket_blocks (optional, n_buckets_cfg entries)
- * overrides each bucket's workgroup size.  The plan owns a small device
- * buffer (graph order and work counters).
+ * overrides each bucket's workgroup size; G nv m must stay below 2^31.  The
+ * plan owns device memory until slaq_batch_destroy: the graph order, work
+ * counters, and result buffers for whatever the caller does not ask for
+ * (alpha, beta, theta, tau2: 32 G nv m bytes; steps; tr L per graph).
  *
  * slaq_batch_run enqueues one persistent launch per bucket on `stream`; each
- * workgroup pulls graphs, most expensive first, and computes degrees, probes,
- * m Lanczos steps, the FP64 Gauss rule and the requested outputs (any may be
- * NULL): heat double[G][nt] (n_g/nv sum tau2 exp(-t theta)), vnge double[G],
- * alpha, beta, theta, tau2 double[G][nv][m], steps int32[G][nv].  With
+ * workgroup pulls graphs, most expensive first, and computes degrees, probes
+ * and m Lanczos steps; then the FP64 Gauss rules of all G nv probes
+ * (slaq_ritz) and, per graph, the requested outputs (any may be NULL): heat
+ * double[G][nt] (n_g/nv sum tau2 exp(-t theta)), vnge double[G], alpha,
+ * beta, theta, tau2 double[G][nv][m], steps int32[G][nv].  With
  * SLAQ_BATCH_GRAPH the launches are captured once into a hipGraph and
- * replayed (re-captured when a buffer pointer or the seed changes).
+ * replayed (re-captured when a buffer pointer or the seed changes).  Runs
+ * that overlap on one plan race on its buffers.
  *
  * slaq_batch_autotune times every workgroup size in {128, 256, 512, 1024}
  * per bucket (median of reps runs, HIP events) and keeps the fastest; the
@@ -337,12 +341,14 @@ slaq_status slaq_closure_apply(const float* yhat, const double* q5, const double
                                const int64_t* graph_n, double tol, double* heat, int* flags, void* stream);
 
 /* Stage timing with HIP events (off by default).  While enabled, every launch
- * of a stage kernel ("spmm_chunks", "spmm_rows", "finalize", "update",
- * "batch_slq", "mlp_*") is bracketed by two events on its stream.
- * slaq_profile_read waits for the recorded events of `kernel` and returns how
- * many launches were recorded and their summed duration in milliseconds;
- * slaq_profile_reset drops the records.  Intended for benchmarks: recording
- * adds two event records per launch. */
+ * of a stage kernel ("spmm_pieces", "spmm_rows", "spmm_heavy", "finalize",
+ * "update", "batch_slq", "mlp_fwd", "mlp_bwd", "mlp_adam", "closure_apply")
+ * is bracketed by two events on its stream; launches captured into a hipGraph
+ * are not timed (replays of the graph neither).  slaq_profile_read waits for
+ * the recorded events of `kernel` and returns how many launches were recorded
+ * and their summed duration in milliseconds; slaq_profile_reset drops the
+ * records.  Intended for benchmarks: recording adds two event records per
+ * launch. */
 slaq_status slaq_profile_enable(int on);
 slaq_status slaq_profile_reset(void);
 slaq_status slaq_profile_read(const char* kernel, int64_t* launches, double* total_ms);

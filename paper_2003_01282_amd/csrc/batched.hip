@@ -1,10 +1,14 @@
 // Batched SLQ for many small graphs (paper §3.1 and Algorithm 1 applied to
-// every graph of a collection): one workgroup computes one whole graph - degrees,
-// probes, m Lanczos steps, the FP64 Gauss rule and the heat trace / VNGE -
-// with the current Lanczos vector in LDS and the previous one and w in
-// registers.  Graphs are grouped into size buckets; each bucket is one
-// persistent launch whose workgroups pull graphs (largest first) from an
-// atomic queue.  All bucket launches of a run are replayed from one hipGraph.
+// every graph of a collection).  One workgroup runs the Lanczos part of one
+// whole graph - degrees, probes, m steps - with the current Lanczos vector in
+// LDS and the previous one and w in registers, and writes alpha, beta, the
+// step counts and tr L.  Graphs are grouped into size buckets; each bucket is
+// one persistent launch whose workgroups pull graphs (largest first) from an
+// atomic queue.  The FP64 Gauss rules of all G nv probes then come from the
+// plain path's eigensolver (one thread per probe), and one block per graph
+// forms the heat trace and VNGE; the FP64 tail lives in kernels of its own so
+// that its registers do not limit the occupancy of the step kernel.  All
+// launches of a run are replayed from one hipGraph.
 //
 // Probe p of graph g is the plain path's probe p for seed + g on that graph
 // alone (SplitMix64 keyed on the graph-local node id), so a graph's batched
@@ -24,6 +28,7 @@
 namespace slaq {
 
 constexpr double kBatchEpsBreakdown = 1e-6;
+constexpr int kBatchUnroll = 4;  // nonzeros of a row gathered per round
 
 __device__ __forceinline__ uint64_t bmix64(uint64_t seed, uint64_t counter) {
     uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
@@ -39,24 +44,20 @@ struct BatchArgs {
     const int64_t* goff;    // node offsets [G+1] (device)
     const int64_t* rp;      // global row_ptr (device)
     const int32_t* col;     // global column ids (device)
-    int nv, m, nt, n_max;
+    int nv, m, n_max;
     uint64_t seed;
-    const double* t;        // [nt]
-    double* heat;           // [G][nt] or NULL
-    double* vnge;           // [G] or NULL
-    double* alpha;          // [G][nv][m] or NULL
-    double* beta;           // [G][nv][m] or NULL
-    int32_t* steps;         // [G][nv] or NULL
-    double* theta;          // [G][nv][m] or NULL
-    double* tau2;           // [G][nv][m] or NULL
+    double* alpha;          // [G][nv][m]
+    double* beta;           // [G][nv][m]
+    int32_t* steps;         // [G][nv]
+    double* trace;          // [G]: tr L (non-isolated node count)
 };
 
 // LDS layout (bytes), n_max nodes, ld = 4F floats per node
 struct BatchLds {
-    size_t r, dinv, al, be, th, w2, ee, st, red, coef, total;
+    size_t r, dinv, st, red, coef, total;
 };
 
-__host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int m, int B) {
+__host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int B) {
     const int F = (nv + 3) / 4;
     BatchLds L{};
     size_t off = 0;
@@ -64,16 +65,6 @@ __host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int m, int B) {
     off += (size_t)n_max * F * 16;
     L.dinv = off;
     off += ((size_t)n_max * 4 + 15) / 16 * 16;
-    L.al = off;
-    off += (size_t)nv * m * 8;
-    L.be = off;
-    off += (size_t)nv * m * 8;
-    L.th = off;
-    off += (size_t)nv * m * 8;
-    L.w2 = off;
-    off += (size_t)nv * m * 8;
-    L.ee = off;
-    off += (size_t)nv * m * 8;
     L.st = off;  // per probe: sigma, tau, a, active, steps (doubles)
     off += (size_t)nv * 40;
     L.red = off;
@@ -89,14 +80,9 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int F = (a.nv + 3) / 4;
     const int ldq = F;  // quads per node
-    const BatchLds L = batch_lds(a.n_max, a.nv, a.m, B);
+    const BatchLds L = batch_lds(a.n_max, a.nv, B);
     float4* R = (float4*)(lds + L.r);
     float* dinv = (float*)(lds + L.dinv);
-    double* al = (double*)(lds + L.al);
-    double* be = (double*)(lds + L.be);
-    double* th = (double*)(lds + L.th);
-    double* w2 = (double*)(lds + L.w2);
-    double* ee = (double*)(lds + L.ee);
     double* pst = (double*)(lds + L.st);  // [nv][5]: sigma, tau, a, active, steps
     double* red = (double*)(lds + L.red);
     float* coef = (float*)(lds + L.coef);  // [3][4F]
@@ -154,10 +140,10 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 pst[5 * p + 4] = (double)a.m;
             }
         }
-        for (int k = t; k < a.nv * a.m; k += B) {
-            al[k] = 0.0;
-            be[k] = 0.0;
-        }
+        // every (probe, step) entry of alpha and beta is written below (0 once
+        // a probe has stopped)
+        double* const gal = a.alpha + (int64_t)g * a.nv * a.m;
+        double* const gbe = a.beta + (int64_t)g * a.nv * a.m;
         __syncthreads();
         if (t == 0) {
             double s = 0.0;
@@ -183,7 +169,32 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 if (!tact || i >= n) continue;
                 const int64_t s = rp[i], e = rp[i + 1];
                 float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-                for (int64_t kk = s; kk < e; ++kk) {
+                int64_t kk = s;
+                // kBatchUnroll column ids, then their LDS reads, are in flight at
+                // once; the products are added in nonzero order as below
+                for (; kk + kBatchUnroll <= e; kk += kBatchUnroll) {
+                    int c[kBatchUnroll];
+#pragma unroll
+                    for (int u = 0; u < kBatchUnroll; ++u) c[u] = (int)(col[kk + u] - base);
+                    float dc[kBatchUnroll];
+                    float4 x[kBatchUnroll];
+#pragma unroll
+                    for (int u = 0; u < kBatchUnroll; ++u) {
+                        const bool in = (unsigned)c[u] < (unsigned)n;  // column outside the graph: ignored
+                        const int cc = in ? c[u] : 0;
+                        dc[u] = in ? dinv[cc] : 0.0f;
+                        x[u] = R[cc * ldq + q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatchUnroll; ++u) {
+                        if ((unsigned)c[u] >= (unsigned)n) continue;
+                        acc.x = fmaf(dc[u], x[u].x, acc.x);
+                        acc.y = fmaf(dc[u], x[u].y, acc.y);
+                        acc.z = fmaf(dc[u], x[u].z, acc.z);
+                        acc.w = fmaf(dc[u], x[u].w, acc.w);
+                    }
+                }
+                for (; kk < e; ++kk) {
                     const int c = (int)(col[kk] - base);
                     if ((unsigned)c >= (unsigned)n) continue;  // column outside the graph: ignored
                     const float dc = dinv[c];
@@ -216,10 +227,11 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
                 if (pst[5 * t + 3] != 0.0) {
                     const double alpha = pst[5 * t + 0] * s;
-                    al[t * a.m + j - 1] = alpha;
+                    gal[t * a.m + j - 1] = alpha;
                     pst[5 * t + 2] = alpha * pst[5 * t + 0];
                     coef[8 * F + t] = (float)pst[5 * t + 2];
                 } else {
+                    gal[t * a.m + j - 1] = 0.0;
                     coef[8 * F + t] = 0.0f;
                 }
             }
@@ -252,9 +264,11 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 const int qq = t >> 2, cc = t & 3;
                 double s = 0.0;
                 for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
-                if (pst[5 * t + 3] != 0.0) {
+                if (pst[5 * t + 3] == 0.0) {
+                    gbe[t * a.m + j - 1] = 0.0;
+                } else {
                     const double b = sqrt(fmax(s, 0.0));
-                    be[t * a.m + j - 1] = b;
+                    gbe[t * a.m + j - 1] = b;
                     if (j < a.m && !(b > kBatchEpsBreakdown * 2.0)) {
                         pst[5 * t + 3] = 0.0;
                         pst[5 * t + 1] = 0.0;
@@ -275,60 +289,8 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
             __syncthreads();
         }
 
-        // ---- Gauss rule per probe (FP64 QR on T_p) --------------------------
-        if (t < a.nv) {
-            const int k = (int)pst[5 * t + 4];
-            double* d = th + t * a.m;
-            double* u = w2 + t * a.m;
-            double* e = ee + t * a.m;
-            for (int i = 0; i < k; ++i) {
-                d[i] = al[t * a.m + i];
-                e[i] = i + 1 < k ? be[t * a.m + i] : 0.0;
-            }
-            tridiag_eig_first_row(d, e, u, k, 1);
-            for (int i = 0; i < k; ++i) u[i] = u[i] * u[i];
-            for (int i = k; i < a.m; ++i) {
-                d[i] = 0.0;
-                u[i] = 0.0;
-            }
-            if (a.steps) a.steps[(int64_t)g * a.nv + t] = k;
-        }
-        __syncthreads();
-        // ---- outputs ---------------------------------------------------------
-        const double scale = (double)n / (double)a.nv;
-        const int cnt = a.nv * a.m;
-        if (a.heat) {
-            for (int b = t; b < a.nt; b += B) {
-                const double tt = a.t[b];
-                double s = 0.0;
-                for (int i = 0; i < cnt; ++i) s += w2[i] * exp(-tt * th[i]);
-                a.heat[(int64_t)g * a.nt + b] = scale * s;
-            }
-        }
-        if (a.alpha || a.theta) {
-            for (int i = t; i < cnt; i += B) {
-                if (a.alpha) a.alpha[(int64_t)g * cnt + i] = al[i];
-                if (a.beta) a.beta[(int64_t)g * cnt + i] = be[i];
-                if (a.theta) a.theta[(int64_t)g * cnt + i] = th[i];
-                if (a.tau2) a.tau2[(int64_t)g * cnt + i] = w2[i];
-            }
-        }
-        if (a.vnge) {
-            const double c = s_scal[0];
-            double s = 0.0;
-            if (c > 0.0)
-                for (int i = t; i < cnt; i += B) {
-                    const double x = th[i] / c;
-                    if (x > 0.0) s += w2[i] * (x * log(x));
-                }
-            red[t] = s;
-            __syncthreads();
-            if (t == 0) {
-                double tot = 0.0;
-                for (int i = 0; i < B; ++i) tot += red[i];
-                a.vnge[g] = -scale * tot;
-            }
-        }
+        if (t < a.nv) a.steps[(int64_t)g * a.nv + t] = (int32_t)pst[5 * t + 4];
+        if (t == 0) a.trace[g] = s_scal[0];
         __syncthreads();
     }
 }
@@ -336,6 +298,49 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
 __global__ void reset_queues(int* q, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) q[i] = 0;
+}
+
+// Per graph from its Gauss rules: heat[g][b] = n_g/nv sum tau2 exp(-t_b theta)
+// and vnge[g] = -n_g/nv sum tau2 g(theta / tr L_g), g(x) = x ln x for x > 0
+// (fixed-order tree for the VNGE sum).  Blocks stride over the graphs.
+__global__ void __launch_bounds__(256) batch_outputs(const int64_t* __restrict__ goff, int64_t G, int nv, int m,
+                                                     const double* __restrict__ theta,
+                                                     const double* __restrict__ tau2,
+                                                     const double* __restrict__ trace, int nt,
+                                                     const double* __restrict__ tgrid, double* __restrict__ heat,
+                                                     double* __restrict__ vnge) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int cnt = nv * m;
+    for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
+        const double scale = (double)(goff[g + 1] - goff[g]) / (double)nv;
+        const double* th = theta + g * cnt;
+        const double* w2 = tau2 + g * cnt;
+        if (heat)
+            for (int b = tid; b < nt; b += 256) {
+                const double tt = tgrid[b];
+                double s = 0.0;
+                for (int i = 0; i < cnt; ++i) s += w2[i] * exp(-tt * th[i]);
+                heat[g * nt + b] = scale * s;
+            }
+        if (vnge) {
+            const double c = trace[g];
+            double s = 0.0;
+            if (c > 0.0)
+                for (int i = tid; i < cnt; i += 256) {
+                    const double x = th[i] / c;
+                    if (x > 0.0) s += w2[i] * (x * log(x));
+                }
+            red[tid] = s;
+            __syncthreads();
+            for (int off = 128; off > 0; off >>= 1) {
+                if (tid < off) red[tid] += red[tid + off];
+                __syncthreads();
+            }
+            if (tid == 0) vnge[g] = -scale * red[0];
+            __syncthreads();
+        }
+    }
 }
 
 // ------------------------------------------------------------- host plan --
@@ -374,6 +379,10 @@ struct slaq_batch_s {
     int32_t* order_dev;             // library-owned
     int* queues_dev;                // library-owned, one counter per bucket
     std::vector<std::vector<int32_t>> order_host;
+    // library-owned results of the last run when the caller passes no buffer:
+    // alpha, beta, theta, tau2 [G][nv][m], steps [G][nv], tr L [G]
+    double *al_dev, *be_dev, *th_dev, *w2_dev, *tr_dev;
+    int32_t* st_dev;
     hipGraphExec_t exec;
     hipGraph_t graph;
     hipStream_t cap;  // private stream used only for capture (the NULL stream cannot be captured)
@@ -382,6 +391,18 @@ struct slaq_batch_s {
 };
 
 namespace slaq {
+
+static void free_plan(slaq_batch_s* b) {
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+    }
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (void* p : {(void*)b->order_dev, (void*)b->queues_dev, (void*)b->al_dev, (void*)b->be_dev,
+                    (void*)b->th_dev, (void*)b->w2_dev, (void*)b->st_dev, (void*)b->tr_dev})
+        if (p) (void)hipFree(p);
+    delete b;
+}
 
 static int device_cus() {
     int dev = 0, cus = 0;
@@ -407,7 +428,7 @@ static slaq_status configure_bucket(BucketCfg& b, int nv, int m, int block) {
                  "no batched kernel for block %d, %d rows per thread (n up to %d)", block, ipt_r, b.n_hi);
     b.block = block;
     b.ipt = ipt_r;
-    b.lds = batch_lds(b.n_hi, nv, m, block).total;
+    b.lds = batch_lds(b.n_hi, nv, block).total;
     SLAQ_REQUIRE(b.lds <= 160 * 1024, SLAQ_ERR_UNSUPPORTED, "graphs of %d nodes need %zu bytes of LDS", b.n_hi, b.lds);
     BatchKernel k = pick_kernel(block, ipt_r);
     int per_cu = 0;
@@ -446,6 +467,8 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
     }
     SLAQ_REQUIRE(nmax <= 8192, SLAQ_ERR_UNSUPPORTED, "batched graphs are limited to 8192 nodes (got %lld)",
                  (long long)nmax);
+    SLAQ_REQUIRE(n_graphs * nv * m <= INT32_MAX, SLAQ_ERR_UNSUPPORTED,
+                 "G * nv * m must stay below 2^31 (got %lld)", (long long)(n_graphs * nv * m));
     std::vector<int> edges = {0, 64};
     while (edges.back() < nmax) edges.push_back(edges.back() * 2);
     slaq_batch_s* b = new (std::nothrow) slaq_batch_s();
@@ -497,16 +520,19 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         b->buckets.push_back(c);
     }
     b->bucket_start.push_back((int)order.size());
+    const size_t coeffs = (size_t)n_graphs * nv * m * sizeof(double);
     if (hipMalloc(&b->order_dev, order.size() * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&b->queues_dev, b->buckets.size() * sizeof(int)) != hipSuccess) {
-        delete b;
+        hipMalloc(&b->queues_dev, b->buckets.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->al_dev, coeffs) != hipSuccess || hipMalloc(&b->be_dev, coeffs) != hipSuccess ||
+        hipMalloc(&b->th_dev, coeffs) != hipSuccess || hipMalloc(&b->w2_dev, coeffs) != hipSuccess ||
+        hipMalloc(&b->st_dev, (size_t)n_graphs * nv * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&b->tr_dev, (size_t)n_graphs * sizeof(double)) != hipSuccess) {
+        free_plan(b);
         set_error("hipMalloc of the batch plan failed");
         return SLAQ_ERR_HIP;
     }
     if (hipMemcpy(b->order_dev, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(b->order_dev);
-        (void)hipFree(b->queues_dev);
-        delete b;
+        free_plan(b);
         set_error("copy of the batch order failed");
         return SLAQ_ERR_HIP;
     }
@@ -530,6 +556,9 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
                                  double* alpha, double* beta, int32_t* steps, double* theta, double* tau2,
                                  hipStream_t st, int only_bucket) {
     const int nbk = (int)b->buckets.size();
+    double* al = alpha ? alpha : b->al_dev;
+    double* be = beta ? beta : b->be_dev;
+    int32_t* sp = steps ? steps : b->st_dev;
     hipLaunchKernelGGL(reset_queues, dim3(1), dim3(64), 0, st, b->queues_dev, nbk);
     SLAQ_LAUNCHED();
     for (int k = 0; k < nbk; ++k) {
@@ -544,20 +573,27 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
         a.col = b->col;
         a.nv = b->nv;
         a.m = b->m;
-        a.nt = b->nt;
         a.n_max = c.n_hi;
         a.seed = seed;
-        a.t = t;
-        a.heat = heat;
-        a.vnge = vnge;
-        a.alpha = alpha;
-        a.beta = beta;
-        a.steps = steps;
-        a.theta = theta;
-        a.tau2 = tau2;
+        a.alpha = al;
+        a.beta = be;
+        a.steps = sp;
+        a.trace = b->tr_dev;
         BatchKernel kern = pick_kernel(c.block, c.ipt);
         const int grid = std::min(c.grid, a.count);
         SLAQ_TIMED("batch_slq", st, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a));
+        SLAQ_LAUNCHED();
+    }
+    if (only_bucket >= 0) return SLAQ_OK;  // autotuner trial: the Lanczos part of one bucket
+    if (!(heat || vnge || theta)) return SLAQ_OK;
+    double* th = theta ? theta : b->th_dev;
+    double* w2 = tau2 ? tau2 : b->w2_dev;
+    SLAQ_TRY(slaq_ritz(al, be, sp, (int)(b->G * b->nv), b->m, th, w2, st));
+    if (heat || vnge) {
+        const int grid = (int)std::min<int64_t>(b->G, 8192);
+        SLAQ_TIMED("batch_outputs", st,
+                   hipLaunchKernelGGL(batch_outputs, dim3(grid), dim3(256), 0, st, b->goff, b->G, b->nv, b->m, th,
+                                      w2, b->tr_dev, b->nt, t, heat, vnge));
         SLAQ_LAUNCHED();
     }
     return SLAQ_OK;
@@ -656,14 +692,7 @@ slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, d
 
 slaq_status slaq_batch_destroy(slaq_batch_t b) {
     if (!b) return SLAQ_OK;
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-    }
-    if (b->cap) (void)hipStreamDestroy(b->cap);
-    (void)hipFree(b->order_dev);
-    (void)hipFree(b->queues_dev);
-    delete b;
+    free_plan(b);
     return SLAQ_OK;
 }
 

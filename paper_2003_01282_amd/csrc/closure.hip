@@ -434,11 +434,6 @@ static slaq_status gemm(const GemmArgs& a, hipStream_t st, const char* tag) {
     return SLAQ_OK;
 }
 
-#define SLAQ_TRY(x)                        \
-    do {                                   \
-        const slaq_status s_ = (x);        \
-        if (s_ != SLAQ_OK) return s_;      \
-    } while (0)
 
 // forward for a batch of B rows: fills z/h of the hidden layers and y
 static slaq_status closure_fwd(slaq_closure_s* c, const bf16* X, int64_t B, char* ws, const ClosureWs& L,

@@ -16,6 +16,13 @@ namespace slaq {
 void set_error(const char* fmt, ...);
 void clear_error();
 
+// returns a non-OK status of a library call to the caller
+#define SLAQ_TRY(x)                   \
+    do {                              \
+        const slaq_status s_ = (x);   \
+        if (s_ != SLAQ_OK) return s_; \
+    } while (0)
+
 #define SLAQ_REQUIRE(cond, code, ...)          \
     do {                                       \
         if (!(cond)) {                         \

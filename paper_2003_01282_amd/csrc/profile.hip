@@ -35,6 +35,10 @@ hipEvent_t take_event() {
 
 int prof_begin(const char* name, hipStream_t st) {
     if (!g_on.load(std::memory_order_relaxed)) return -1;
+    // launches being captured into a hipGraph are not timed: an event
+    // recorded during capture becomes a graph node, not a timestamp
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
     std::lock_guard<std::mutex> lk(g_mu);
     Record r{name, take_event(), take_event()};
     if (!r.start || !r.stop) return -1;
