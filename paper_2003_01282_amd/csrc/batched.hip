@@ -2,7 +2,9 @@
 // every graph of a collection).  One workgroup runs the Lanczos part of one
 // whole graph - degrees, probes, m steps - with the current Lanczos vector in
 // LDS and the previous one and w in registers, and writes alpha, beta, the
-// step counts and tr L.  Graphs are grouped into size buckets; each bucket is
+// step counts and tr L.  As in the plain path the vectors of rows with edges
+// are kept in the scaled basis X = D^-1/2 R, so a gather adds neighbour rows
+// with no per-nonzero scale (isolated rows keep R: L is zero there).  Graphs are grouped into size buckets; each bucket is
 // one persistent launch whose workgroups pull graphs (largest first) from an
 // atomic queue.  The FP64 Gauss rules of all G nv probes then come from the
 // plain path's eigensolver (one thread per probe), and one block per graph
@@ -115,15 +117,18 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
             nonzero += d > 0 ? 1 : 0;
         }
         red[t] = (double)nonzero;
-        // ---- probes R_1 = v (graph-local ids, seed + g) ----------------------
+        // ---- probes R_1 = v (graph-local ids, seed + g), stored as X_1 = D^-1/2 v
+        //      on rows with edges --------------------------------------------------
         const uint64_t sg = a.seed + (uint64_t)g;
         for (int x = t; x < n * F; x += B) {
             const int i = x / F, qq = x % F, p0 = 4 * qq;
+            const int64_t d = rp[i + 1] - rp[i];
+            const float one = d > 0 ? (float)(1.0 / sqrt((double)d)) : 1.0f;  // the same value as dinv[i]
             const uint64_t z = bmix64(sg, 64ull * (uint64_t)i + (uint64_t)(p0 >> 6));
             float v[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -1.0f : 1.0f) : 0.0f;
+                v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -one : one) : 0.0f;
             R[x] = make_float4(v[0], v[1], v[2], v[3]);
         }
         const double sigma1 = 1.0 / sqrt((double)n);
@@ -176,47 +181,49 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                     int c[kBatchUnroll];
 #pragma unroll
                     for (int u = 0; u < kBatchUnroll; ++u) c[u] = (int)(col[kk + u] - base);
-                    float dc[kBatchUnroll];
                     float4 x[kBatchUnroll];
 #pragma unroll
                     for (int u = 0; u < kBatchUnroll; ++u) {
                         const bool in = (unsigned)c[u] < (unsigned)n;  // column outside the graph: ignored
-                        const int cc = in ? c[u] : 0;
-                        dc[u] = in ? dinv[cc] : 0.0f;
-                        x[u] = R[cc * ldq + q];
+                        x[u] = in ? R[c[u] * ldq + q] : make_float4(0.f, 0.f, 0.f, 0.f);
                     }
 #pragma unroll
                     for (int u = 0; u < kBatchUnroll; ++u) {
-                        if ((unsigned)c[u] >= (unsigned)n) continue;
-                        acc.x = fmaf(dc[u], x[u].x, acc.x);
-                        acc.y = fmaf(dc[u], x[u].y, acc.y);
-                        acc.z = fmaf(dc[u], x[u].z, acc.z);
-                        acc.w = fmaf(dc[u], x[u].w, acc.w);
+                        acc.x += x[u].x;
+                        acc.y += x[u].y;
+                        acc.z += x[u].z;
+                        acc.w += x[u].w;
                     }
                 }
                 for (; kk < e; ++kk) {
                     const int c = (int)(col[kk] - base);
                     if ((unsigned)c >= (unsigned)n) continue;  // column outside the graph: ignored
-                    const float dc = dinv[c];
                     const float4 x = R[c * ldq + q];
-                    acc.x = fmaf(dc, x.x, acc.x);
-                    acc.y = fmaf(dc, x.y, acc.y);
-                    acc.z = fmaf(dc, x.z, acc.z);
-                    acc.w = fmaf(dc, x.w, acc.w);
+                    acc.x += x.x;
+                    acc.y += x.y;
+                    acc.z += x.z;
+                    acc.w += x.w;
                 }
+                // rows with edges: D^-1/2 w = sigma (X_i - dinv_i^2 (A X)_i) - tau X_{j-1,i}
+                // in FP64 with one rounding, dot weight 1/dinv_i^2; isolated rows
+                // (unscaled): L R = 0, w = -tau R_{j-1,i}, weight 1
                 const float di = dinv[i];
-                const float nz = e > s ? 1.0f : 0.0f;
+                const double dd = (double)di, d2 = dd * dd, wgt = di != 0.0f ? 1.0 / d2 : 1.0;
                 const float4 ri = R[i * ldq + q];
+                const float* rv = &ri.x;
+                const float* av = &acc.x;
+                const float* pv = &prev[k].x;
+                const float* sv = &sgm.x;
+                const float* tv = &tau.x;
                 float4 w;
-                w.x = fmaf(-tau.x, prev[k].x, sgm.x * fmaf(-di, acc.x, nz * ri.x));
-                w.y = fmaf(-tau.y, prev[k].y, sgm.y * fmaf(-di, acc.y, nz * ri.y));
-                w.z = fmaf(-tau.z, prev[k].z, sgm.z * fmaf(-di, acc.z, nz * ri.z));
-                w.w = fmaf(-tau.w, prev[k].w, sgm.w * fmaf(-di, acc.w, nz * ri.w));
+                float* wp = &w.x;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double lr = di != 0.0f ? fma(-d2, (double)av[c], (double)rv[c]) : 0.0;
+                    wp[c] = (float)fma(-(double)tv[c], (double)pv[c], (double)sv[c] * lr);
+                    s1[c] = fma((double)rv[c] * (double)wp[c], wgt, s1[c]);
+                }
                 wv[k] = w;
-                s1[0] = fma((double)ri.x, (double)w.x, s1[0]);
-                s1[1] = fma((double)ri.y, (double)w.y, s1[1]);
-                s1[2] = fma((double)ri.z, (double)w.z, s1[2]);
-                s1[3] = fma((double)ri.w, (double)w.w, s1[3]);
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s1[c];
@@ -245,6 +252,8 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 const int i = row0 + k * rstride;
                 if (!tact || i >= n) continue;
                 const float4 ri = R[i * ldq + q];
+                const float di = dinv[i];
+                const double wgt = di != 0.0f ? 1.0 / ((double)di * (double)di) : 1.0;  // ||R||^2 from X
                 float4 r;
                 r.x = fmaf(-av.x, ri.x, wv[k].x);
                 r.y = fmaf(-av.y, ri.y, wv[k].y);
@@ -252,10 +261,10 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 r.w = fmaf(-av.w, ri.w, wv[k].w);
                 prev[k] = ri;
                 R[i * ldq + q] = r;
-                s2[0] = fma((double)r.x, (double)r.x, s2[0]);
-                s2[1] = fma((double)r.y, (double)r.y, s2[1]);
-                s2[2] = fma((double)r.z, (double)r.z, s2[2]);
-                s2[3] = fma((double)r.w, (double)r.w, s2[3]);
+                s2[0] = fma((double)r.x * (double)r.x, wgt, s2[0]);
+                s2[1] = fma((double)r.y * (double)r.y, wgt, s2[1]);
+                s2[2] = fma((double)r.z * (double)r.z, wgt, s2[2]);
+                s2[3] = fma((double)r.w * (double)r.w, wgt, s2[3]);
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s2[c];

@@ -18,11 +18,14 @@ T = O.t_grid(256)
 
 def mixed_batch(count, seed):
     gs = inputs.small_graph_mix(count, seed=seed)
-    # degenerate members: a single node, no edges, a complete graph, a star
+    # degenerate members: a single node, no edges, a complete graph, a star,
+    # a star followed by isolated nodes (rows with and without edges mixed)
     gs[3] = inputs.CSR(n=1, row_ptr=np.zeros(2, dtype=np.int64), col_idx=np.zeros(0, dtype=np.int32))
     gs[5] = inputs.CSR(n=9, row_ptr=np.zeros(10, dtype=np.int64), col_idx=np.zeros(0, dtype=np.int32))
     gs[7] = inputs.complete(40)
     gs[9] = inputs.star(300)
+    st = inputs.star(50)
+    gs[11] = inputs.CSR(n=80, row_ptr=np.r_[st.row_ptr, np.full(30, st.nnz, dtype=np.int64)], col_idx=st.col_idx)
     return gs
 
 
