@@ -248,7 +248,11 @@ slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, i
  * (each row's columns lie inside its own graph).  Graph g uses the probes of
  * slaq_lanczos with seed + g on that graph alone (keys are graph-local node
  * ids), so each output row equals the plain path on the graph by itself, up
- * to summation order.  Normalized Laplacian; n_g <= 8192, nv <= 256.
+ * to summation order.  Normalized Laplacian; nv <= 256; fewer than 2^31
+ * nodes in the whole batch.  A bucket whose probe block (n_hi ceil(nv/4) 16
+ * bytes) fits in 64 KB keeps it in LDS; larger graphs run the same
+ * per-graph Lanczos with the probe blocks in a plan-owned global workspace
+ * (up to 8 GB: slots of 3 n_hi ceil(nv/4) 16 + 4 n_hi bytes).
  *
  * slaq_batch_plan (host): node_off and nnz_off are HOST copies of the node
  * offsets and of row_ptr at the graph starts (G+1 entries each);
@@ -270,6 +274,11 @@ slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, i
  * replayed (re-captured when a buffer pointer or the seed changes).  Runs
  * that overlap on one plan race on its buffers.
  *
+ * slaq_batch_buckets reports the bucket count and, per bucket (arrays of
+ * n_buckets entries, any may be NULL), its largest node count, workgroup
+ * size, graph count and whether its probe blocks live in LDS (1) or in the
+ * global workspace (0).
+ *
  * slaq_batch_autotune times every workgroup size in {128, 256, 512, 1024}
  * per bucket (median of reps runs, HIP events) and keeps the fastest; the
  * chosen sizes are returned in blocks_out[n_buckets] (optional). */
@@ -279,7 +288,8 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
                             const int64_t* node_off_dev, const int64_t* row_ptr,
                             const int32_t* col_idx, int nv, int m, int nt,
                             const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out);
-slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* blocks, int* graphs);
+slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* blocks, int* graphs,
+                               int* in_lds);
 slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, double* heat, double* vnge,
                            double* alpha, double* beta, int32_t* steps, double* theta, double* tau2,
                            unsigned flags, void* stream);

@@ -77,6 +77,74 @@ __host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int B) {
     return L;
 }
 
+// Per-graph recurrence state (LDS): pst[5 p ..] = sigma, tau, a, active,
+// steps of probe p; coef[4F] x 3 = sigma, tau, a in FP32 for the vector math.
+__device__ __forceinline__ void init_probe_state(int t, int B, int nv, int F, int m, double sigma1, double* pst,
+                                                 float* coef) {
+    for (int p = t; p < 4 * F; p += B) {
+        const bool on = p < nv;
+        coef[p] = on ? (float)sigma1 : 0.0f;
+        coef[4 * F + p] = 0.0f;
+        coef[8 * F + p] = 0.0f;
+        if (on) {
+            pst[5 * p + 0] = sigma1;
+            pst[5 * p + 1] = 0.0;
+            pst[5 * p + 2] = 0.0;
+            pst[5 * p + 3] = 1.0;
+            pst[5 * p + 4] = (double)m;
+        }
+    }
+}
+
+// alpha_j of probe t (t < nv) from the block's FP64 partial dot products
+// red[4 u + c] (threads u = q, q + F, ..., fixed order); writes gal[t m + j-1]
+// (0 once the probe has stopped) and the FP32 update coefficient a_j.
+__device__ __forceinline__ void finish_alpha(int t, int F, int bact, int m, int j, const double* red, double* pst,
+                                             float* coef, double* gal) {
+    const int qq = t >> 2, cc = t & 3;
+    double s = 0.0;
+    for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
+    if (pst[5 * t + 3] != 0.0) {
+        const double alpha = pst[5 * t + 0] * s;
+        gal[t * m + j - 1] = alpha;
+        pst[5 * t + 2] = alpha * pst[5 * t + 0];
+        coef[8 * F + t] = (float)pst[5 * t + 2];
+    } else {
+        gal[t * m + j - 1] = 0.0;
+        coef[8 * F + t] = 0.0f;
+    }
+}
+
+// beta_j = ||R_{j+1}|| of probe t, the breakdown test and the next step's
+// sigma and tau; writes gbe[t m + j-1] (0 once the probe has stopped).
+__device__ __forceinline__ void finish_beta(int t, int F, int bact, int m, int j, const double* red, double* pst,
+                                            float* coef, double* gbe) {
+    const int qq = t >> 2, cc = t & 3;
+    double s = 0.0;
+    for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
+    if (pst[5 * t + 3] == 0.0) {
+        gbe[t * m + j - 1] = 0.0;
+        return;
+    }
+    const double b = sqrt(fmax(s, 0.0));
+    gbe[t * m + j - 1] = b;
+    if (j < m && !(b > kBatchEpsBreakdown * 2.0)) {
+        pst[5 * t + 3] = 0.0;
+        pst[5 * t + 1] = 0.0;
+        pst[5 * t + 0] = 0.0;
+        coef[t] = 0.0f;
+        coef[4 * F + t] = 0.0f;
+        coef[8 * F + t] = 0.0f;
+        pst[5 * t + 4] = (double)j;
+    } else {
+        const double tn = b * pst[5 * t + 0];
+        pst[5 * t + 1] = tn;
+        pst[5 * t + 0] = 1.0 / b;
+        coef[t] = (float)(1.0 / b);
+        coef[4 * F + t] = (float)tn;
+    }
+}
+
 template <int B, int IPT>
 __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -131,20 +199,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -one : one) : 0.0f;
             R[x] = make_float4(v[0], v[1], v[2], v[3]);
         }
-        const double sigma1 = 1.0 / sqrt((double)n);
-        for (int p = t; p < 4 * F; p += B) {
-            const bool on = p < a.nv;
-            coef[p] = on ? (float)sigma1 : 0.0f;
-            coef[4 * F + p] = 0.0f;
-            coef[8 * F + p] = 0.0f;
-            if (on) {
-                pst[5 * p + 0] = sigma1;
-                pst[5 * p + 1] = 0.0;
-                pst[5 * p + 2] = 0.0;
-                pst[5 * p + 3] = 1.0;
-                pst[5 * p + 4] = (double)a.m;
-            }
-        }
+        init_probe_state(t, B, a.nv, F, a.m, 1.0 / sqrt((double)n), pst, coef);
         // every (probe, step) entry of alpha and beta is written below (0 once
         // a probe has stopped)
         double* const gal = a.alpha + (int64_t)g * a.nv * a.m;
@@ -228,20 +283,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s1[c];
             __syncthreads();
-            if (t < a.nv) {
-                const int qq = t >> 2, cc = t & 3;
-                double s = 0.0;
-                for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
-                if (pst[5 * t + 3] != 0.0) {
-                    const double alpha = pst[5 * t + 0] * s;
-                    gal[t * a.m + j - 1] = alpha;
-                    pst[5 * t + 2] = alpha * pst[5 * t + 0];
-                    coef[8 * F + t] = (float)pst[5 * t + 2];
-                } else {
-                    gal[t * a.m + j - 1] = 0.0;
-                    coef[8 * F + t] = 0.0f;
-                }
-            }
+            if (t < a.nv) finish_alpha(t, F, bact, a.m, j, red, pst, coef, gal);
             __syncthreads();
             // ---- R_{j+1} = w - a R_j (in place); partial ||R_{j+1}||^2 ---------
             const float4 av = make_float4(coef[8 * F + 4 * q], coef[8 * F + 4 * q + 1], coef[8 * F + 4 * q + 2],
@@ -269,35 +311,177 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s2[c];
             __syncthreads();
-            if (t < a.nv) {
-                const int qq = t >> 2, cc = t & 3;
-                double s = 0.0;
-                for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
-                if (pst[5 * t + 3] == 0.0) {
-                    gbe[t * a.m + j - 1] = 0.0;
-                } else {
-                    const double b = sqrt(fmax(s, 0.0));
-                    gbe[t * a.m + j - 1] = b;
-                    if (j < a.m && !(b > kBatchEpsBreakdown * 2.0)) {
-                        pst[5 * t + 3] = 0.0;
-                        pst[5 * t + 1] = 0.0;
-                        pst[5 * t + 0] = 0.0;
-                        coef[t] = 0.0f;
-                        coef[4 * F + t] = 0.0f;
-                        coef[8 * F + t] = 0.0f;
-                        pst[5 * t + 4] = (double)j;
-                    } else {
-                        const double tn = b * pst[5 * t + 0];
-                        pst[5 * t + 1] = tn;
-                        pst[5 * t + 0] = 1.0 / b;
-                        coef[t] = (float)(1.0 / b);
-                        coef[4 * F + t] = (float)tn;
-                    }
-                }
-            }
+            if (t < a.nv) finish_beta(t, F, bact, a.m, j, red, pst, coef, gbe);
             __syncthreads();
         }
 
+        if (t < a.nv) a.steps[(int64_t)g * a.nv + t] = (int32_t)pst[5 * t + 4];
+        if (t == 0) a.trace[g] = s_scal[0];
+        __syncthreads();
+    }
+}
+
+// Graphs whose probe block does not fit in LDS: the same per-graph Lanczos
+// with X_j, X_{j-1}, w and D^-1/2 in the workgroup's slot of a global
+// workspace (slot = blockIdx.x, slot_quads quads per block, slot_n floats of
+// D^-1/2).  Rows are taken in passes of bact / F; nothing is held per row in
+// registers, so the kernel serves any graph size.  X_{j+1} overwrites
+// X_{j-1}, and the two buffers swap roles after every step.
+template <int B>
+__global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __restrict__ ws, int64_t slot_quads,
+                                                      float* __restrict__ wsd, int64_t slot_n) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int F = (a.nv + 3) / 4;
+    const BatchLds L = batch_lds(0, a.nv, B);
+    double* pst = (double*)(lds + L.st);
+    double* red = (double*)(lds + L.red);
+    float* coef = (float*)(lds + L.coef);
+    __shared__ int s_job;
+    __shared__ double s_scal[4];
+
+    const int t = threadIdx.x;
+    const int bact = (B / F) * F;
+    const bool tact = t < bact;
+    const int q = t % F;
+    const int row0 = t / F;
+    const int rstride = bact / F;
+    float4* const slot = ws + (int64_t)blockIdx.x * 3 * slot_quads;
+    float* const dinv = wsd + (int64_t)blockIdx.x * slot_n;
+
+    for (;;) {
+        if (t == 0) s_job = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int job = s_job;
+        if (job >= a.count) break;
+        const int g = a.order[job];
+        const int64_t base = a.goff[g];
+        const int n = (int)(a.goff[g + 1] - base);
+        const int64_t* rp = a.rp + base;
+        const int32_t* col = a.col;
+        float4* X = slot;                    // X_j
+        float4* P = slot + slot_quads;       // X_{j-1}, then X_{j+1}
+        float4* W = slot + 2 * slot_quads;   // D^-1/2 w
+
+        int nonzero = 0;
+        for (int i = t; i < n; i += B) {
+            const int64_t d = rp[i + 1] - rp[i];
+            dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
+            nonzero += d > 0 ? 1 : 0;
+        }
+        red[t] = (double)nonzero;
+        const uint64_t sg = a.seed + (uint64_t)g;
+        for (int64_t x = t; x < (int64_t)n * F; x += B) {
+            const int i = (int)(x / F), qq = (int)(x % F), p0 = 4 * qq;
+            const int64_t d = rp[i + 1] - rp[i];
+            const float one = d > 0 ? (float)(1.0 / sqrt((double)d)) : 1.0f;
+            const uint64_t z = bmix64(sg, 64ull * (uint64_t)i + (uint64_t)(p0 >> 6));
+            float v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -one : one) : 0.0f;
+            X[x] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        init_probe_state(t, B, a.nv, F, a.m, 1.0 / sqrt((double)n), pst, coef);
+        double* const gal = a.alpha + (int64_t)g * a.nv * a.m;
+        double* const gbe = a.beta + (int64_t)g * a.nv * a.m;
+        __syncthreads();
+        if (t == 0) {
+            double s = 0.0;
+            for (int i = 0; i < B; ++i) s += red[i];
+            s_scal[0] = s;
+        }
+        __syncthreads();
+
+        for (int j = 1; j <= a.m; ++j) {
+            const float4 sgm = make_float4(coef[4 * q], coef[4 * q + 1], coef[4 * q + 2], coef[4 * q + 3]);
+            const float4 tau = make_float4(coef[4 * F + 4 * q], coef[4 * F + 4 * q + 1], coef[4 * F + 4 * q + 2],
+                                           coef[4 * F + 4 * q + 3]);
+            double s1[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = row0; tact && i < n; i += rstride) {
+                const int64_t s = rp[i], e = rp[i + 1];
+                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                int64_t kk = s;
+                for (; kk + kBatchUnroll <= e; kk += kBatchUnroll) {
+                    int c[kBatchUnroll];
+#pragma unroll
+                    for (int u = 0; u < kBatchUnroll; ++u) c[u] = (int)(col[kk + u] - base);
+                    float4 x[kBatchUnroll];
+#pragma unroll
+                    for (int u = 0; u < kBatchUnroll; ++u) {
+                        const bool in = (unsigned)c[u] < (unsigned)n;  // column outside the graph: ignored
+                        x[u] = in ? X[(int64_t)c[u] * F + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatchUnroll; ++u) {
+                        acc.x += x[u].x;
+                        acc.y += x[u].y;
+                        acc.z += x[u].z;
+                        acc.w += x[u].w;
+                    }
+                }
+                for (; kk < e; ++kk) {
+                    const int c = (int)(col[kk] - base);
+                    if ((unsigned)c >= (unsigned)n) continue;
+                    const float4 x = X[(int64_t)c * F + q];
+                    acc.x += x.x;
+                    acc.y += x.y;
+                    acc.z += x.z;
+                    acc.w += x.w;
+                }
+                const float di = dinv[i];
+                const double dd = (double)di, d2 = dd * dd, wgt = di != 0.0f ? 1.0 / d2 : 1.0;
+                const int64_t at = (int64_t)i * F + q;
+                const float4 ri = X[at];
+                const float4 pr = j > 1 ? P[at] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float* rv = &ri.x;
+                const float* av = &acc.x;
+                const float* pv = &pr.x;
+                const float* sv = &sgm.x;
+                const float* tv = &tau.x;
+                float4 w;
+                float* wp = &w.x;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double lr = di != 0.0f ? fma(-d2, (double)av[c], (double)rv[c]) : 0.0;
+                    wp[c] = (float)fma(-(double)tv[c], (double)pv[c], (double)sv[c] * lr);
+                    s1[c] = fma((double)rv[c] * (double)wp[c], wgt, s1[c]);
+                }
+                W[at] = w;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[4 * t + c] = s1[c];
+            __syncthreads();
+            if (t < a.nv) finish_alpha(t, F, bact, a.m, j, red, pst, coef, gal);
+            __syncthreads();
+            const float4 av = make_float4(coef[8 * F + 4 * q], coef[8 * F + 4 * q + 1], coef[8 * F + 4 * q + 2],
+                                          coef[8 * F + 4 * q + 3]);
+            double s2[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = row0; tact && i < n; i += rstride) {
+                const int64_t at = (int64_t)i * F + q;
+                const float4 ri = X[at];
+                const float4 wv = W[at];
+                const float di = dinv[i];
+                const double wgt = di != 0.0f ? 1.0 / ((double)di * (double)di) : 1.0;
+                float4 r;
+                r.x = fmaf(-av.x, ri.x, wv.x);
+                r.y = fmaf(-av.y, ri.y, wv.y);
+                r.z = fmaf(-av.z, ri.z, wv.z);
+                r.w = fmaf(-av.w, ri.w, wv.w);
+                P[at] = r;
+                s2[0] = fma((double)r.x * (double)r.x, wgt, s2[0]);
+                s2[1] = fma((double)r.y * (double)r.y, wgt, s2[1]);
+                s2[2] = fma((double)r.z * (double)r.z, wgt, s2[2]);
+                s2[3] = fma((double)r.w * (double)r.w, wgt, s2[3]);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[4 * t + c] = s2[c];
+            __syncthreads();
+            if (t < a.nv) finish_beta(t, F, bact, a.m, j, red, pst, coef, gbe);
+            __syncthreads();
+            float4* const tmp = X;  // X_{j+1} now lives in P; X_j becomes the previous block
+            X = P;
+            P = tmp;
+        }
         if (t < a.nv) a.steps[(int64_t)g * a.nv + t] = (int32_t)pst[5 * t + 4];
         if (t == 0) a.trace[g] = s_scal[0];
         __syncthreads();
@@ -356,12 +540,32 @@ __global__ void __launch_bounds__(256) batch_outputs(const int64_t* __restrict__
 struct BucketCfg {
     int n_lo, n_hi;   // graphs with n in (n_lo, n_hi]
     int block;        // threads per workgroup
-    int ipt;          // items per thread (ceil(n_hi*F / active threads))
+    int ipt;          // items per thread (ceil(n_hi*F / active threads)); 0 for global buckets
     int grid;         // persistent workgroups
     size_t lds;
+    bool global;      // probe blocks in the global workspace (batch_slq_global)
+    int slots;        // workspace slots of a global bucket (caps its grid)
 };
 
 typedef void (*BatchKernel)(BatchArgs);
+typedef void (*BatchGlobalKernel)(BatchArgs, float4*, int64_t, float*, int64_t);
+
+// probe blocks above this size go to the global-workspace kernel (an LDS
+// block this large would leave one workgroup per CU)
+constexpr size_t kLdsVecMax = 64 * 1024;
+// global workspace of a plan: slots of 3 n_hi F quads + n_hi floats, as many
+// as fit this budget (at most 8 per CU), for the largest global bucket
+constexpr size_t kGlobalWsBudget = size_t(8) << 30;
+
+static BatchGlobalKernel pick_global(int block) {
+    switch (block) {
+        case 128: return batch_slq_global<128>;
+        case 256: return batch_slq_global<256>;
+        case 512: return batch_slq_global<512>;
+        case 1024: return batch_slq_global<1024>;
+        default: return nullptr;
+    }
+}
 
 static BatchKernel pick_kernel(int block, int ipt) {
 #define SLAQ_BK(Bv, Iv) if (block == Bv && ipt <= Iv) return batch_slq<Bv, Iv>;
@@ -392,6 +596,10 @@ struct slaq_batch_s {
     // alpha, beta, theta, tau2 [G][nv][m], steps [G][nv], tr L [G]
     double *al_dev, *be_dev, *th_dev, *w2_dev, *tr_dev;
     int32_t* st_dev;
+    // workspace of the global buckets (probe blocks and D^-1/2 per slot)
+    float4* gws;
+    float* gwsd;
+    int64_t ws_quads, ws_floats;
     hipGraphExec_t exec;
     hipGraph_t graph;
     hipStream_t cap;  // private stream used only for capture (the NULL stream cannot be captured)
@@ -408,7 +616,8 @@ static void free_plan(slaq_batch_s* b) {
     }
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (void* p : {(void*)b->order_dev, (void*)b->queues_dev, (void*)b->al_dev, (void*)b->be_dev,
-                    (void*)b->th_dev, (void*)b->w2_dev, (void*)b->st_dev, (void*)b->tr_dev})
+                    (void*)b->th_dev, (void*)b->w2_dev, (void*)b->st_dev, (void*)b->tr_dev, (void*)b->gws,
+                    (void*)b->gwsd})
         if (p) (void)hipFree(p);
     delete b;
 }
@@ -421,9 +630,22 @@ static int device_cus() {
 }
 
 static slaq_status configure_bucket(BucketCfg& b, int nv, int m, int block) {
+    (void)m;
     const int F = (nv + 3) / 4;
     const int bact = (block / F) * F;
     SLAQ_REQUIRE(bact >= F && bact >= nv, SLAQ_ERR_UNSUPPORTED, "block %d too small for nv=%d", block, nv);
+    if (b.global) {
+        BatchGlobalKernel k = pick_global(block);
+        SLAQ_REQUIRE(k, SLAQ_ERR_UNSUPPORTED, "no global batched kernel for block %d", block);
+        b.block = block;
+        b.ipt = 0;
+        b.lds = batch_lds(0, nv, block).total;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, b.lds) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        b.grid = std::min(device_cus() * per_cu, b.slots);
+        return SLAQ_OK;
+    }
     const int rows_per_pass = bact / F;
     const int ipt = (b.n_hi + rows_per_pass - 1) / rows_per_pass;
     static const int sizes[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
@@ -474,11 +696,11 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         SLAQ_REQUIRE(nnz_off[g + 1] >= nnz_off[g], SLAQ_ERR_INVALID_ARG, "nnz offsets decrease at %lld", (long long)g);
         nmax = std::max(nmax, n);
     }
-    SLAQ_REQUIRE(nmax <= 8192, SLAQ_ERR_UNSUPPORTED, "batched graphs are limited to 8192 nodes (got %lld)",
-                 (long long)nmax);
+    SLAQ_REQUIRE(node_off[n_graphs] <= INT32_MAX, SLAQ_ERR_UNSUPPORTED,
+                 "a batch holds fewer than 2^31 nodes in all (column ids are int32)");
     SLAQ_REQUIRE(n_graphs * nv * m <= INT32_MAX, SLAQ_ERR_UNSUPPORTED,
                  "G * nv * m must stay below 2^31 (got %lld)", (long long)(n_graphs * nv * m));
-    std::vector<int> edges = {0, 64};
+    std::vector<int64_t> edges = {0, 64};
     while (edges.back() < nmax) edges.push_back(edges.back() * 2);
     slaq_batch_s* b = new (std::nothrow) slaq_batch_s();
     SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "out of host memory");
@@ -506,11 +728,20 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
                              return x.first > y.first;
                          });
         BucketCfg c{};
-        c.n_lo = edges[k];
+        c.n_lo = (int)edges[k];
         c.n_hi = std::min<int64_t>(edges[k + 1], nmax);
         int64_t top = 0;
         for (auto& pr : members[k]) top = std::max<int64_t>(top, node_off[pr.second + 1] - node_off[pr.second]);
         c.n_hi = (int)top;
+        const int Fq = (nv + 3) / 4;
+        c.global = (size_t)c.n_hi * Fq * 16 > kLdsVecMax;
+        if (c.global) {
+            const size_t slot_bytes = (size_t)3 * c.n_hi * Fq * 16 + (size_t)c.n_hi * 4;
+            c.slots = (int)std::max<size_t>(1, std::min<size_t>(kGlobalWsBudget / slot_bytes,
+                                                                (size_t)device_cus() * 8));
+            b->ws_quads = std::max<int64_t>(b->ws_quads, (int64_t)c.slots * 3 * c.n_hi * Fq);
+            b->ws_floats = std::max<int64_t>(b->ws_floats, (int64_t)c.slots * c.n_hi);
+        }
         const int bidx = (int)b->buckets.size();
         int block = c.n_hi <= 64 ? 128 : (c.n_hi <= 256 ? 256 : 512);
         if (bucket_blocks && bidx < n_buckets_cfg && bucket_blocks[bidx] > 0) block = bucket_blocks[bidx];
@@ -535,7 +766,9 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         hipMalloc(&b->al_dev, coeffs) != hipSuccess || hipMalloc(&b->be_dev, coeffs) != hipSuccess ||
         hipMalloc(&b->th_dev, coeffs) != hipSuccess || hipMalloc(&b->w2_dev, coeffs) != hipSuccess ||
         hipMalloc(&b->st_dev, (size_t)n_graphs * nv * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&b->tr_dev, (size_t)n_graphs * sizeof(double)) != hipSuccess) {
+        hipMalloc(&b->tr_dev, (size_t)n_graphs * sizeof(double)) != hipSuccess ||
+        (b->ws_quads > 0 && hipMalloc(&b->gws, (size_t)b->ws_quads * sizeof(float4)) != hipSuccess) ||
+        (b->ws_floats > 0 && hipMalloc(&b->gwsd, (size_t)b->ws_floats * sizeof(float)) != hipSuccess)) {
         free_plan(b);
         set_error("hipMalloc of the batch plan failed");
         return SLAQ_ERR_HIP;
@@ -549,7 +782,7 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
     return SLAQ_OK;
 }
 
-slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* blocks, int* graphs) {
+slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* blocks, int* graphs, int* in_lds) {
     clear_error();
     SLAQ_REQUIRE(b && n_buckets, SLAQ_ERR_INVALID_ARG, "NULL argument");
     *n_buckets = (int)b->buckets.size();
@@ -557,6 +790,7 @@ slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* b
         if (n_hi) n_hi[k] = b->buckets[k].n_hi;
         if (blocks) blocks[k] = b->buckets[k].block;
         if (graphs) graphs[k] = b->bucket_start[k + 1] - b->bucket_start[k];
+        if (in_lds) in_lds[k] = b->buckets[k].global ? 0 : 1;
     }
     return SLAQ_OK;
 }
@@ -588,9 +822,17 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
         a.beta = be;
         a.steps = sp;
         a.trace = b->tr_dev;
-        BatchKernel kern = pick_kernel(c.block, c.ipt);
         const int grid = std::min(c.grid, a.count);
-        SLAQ_TIMED("batch_slq", st, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a));
+        if (c.global) {
+            const int Fq = (b->nv + 3) / 4;
+            BatchGlobalKernel kern = pick_global(c.block);
+            SLAQ_TIMED("batch_slq", st,
+                       hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a, b->gws,
+                                          (int64_t)c.n_hi * Fq, b->gwsd, (int64_t)c.n_hi));
+        } else {
+            BatchKernel kern = pick_kernel(c.block, c.ipt);
+            SLAQ_TIMED("batch_slq", st, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a));
+        }
         SLAQ_LAUNCHED();
     }
     if (only_bucket >= 0) return SLAQ_OK;  // autotuner trial: the Lanczos part of one bucket

@@ -60,7 +60,7 @@ SIGNATURES = {
     "slaq_signature": [_vp, _vp, _int, _int, _i64, _vp, _int, _int, _vp, _vp],
     "slaq_vnge": [_vp, _vp, _vp, _int, _int, _vp, _vp],
     "slaq_batch_plan": [_i64, _vp, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _int, ctypes.POINTER(_vp)],
-    "slaq_batch_buckets": [_vp, ctypes.POINTER(_int), _vp, _vp, _vp],
+    "slaq_batch_buckets": [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp],
     "slaq_batch_run": [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
     "slaq_batch_autotune": [_vp, _vp, _vp, _vp, _int, _vp, _vp, _vp],
     "slaq_batch_destroy": [_vp],
@@ -335,11 +335,12 @@ class Batch:
 
     def buckets(self):
         nb = _int()
-        _check(lib().slaq_batch_buckets(self.handle, ctypes.byref(nb), None, None, None))
+        _check(lib().slaq_batch_buckets(self.handle, ctypes.byref(nb), None, None, None, None))
         k = nb.value
-        n_hi, blocks, graphs = (ctypes.c_int * k)(), (ctypes.c_int * k)(), (ctypes.c_int * k)()
-        _check(lib().slaq_batch_buckets(self.handle, ctypes.byref(nb), n_hi, blocks, graphs))
-        return [{"n_hi": n_hi[i], "block": blocks[i], "graphs": graphs[i]} for i in range(k)]
+        n_hi, blocks, graphs, lds = [(ctypes.c_int * k)() for _ in range(4)]
+        _check(lib().slaq_batch_buckets(self.handle, ctypes.byref(nb), n_hi, blocks, graphs, lds))
+        return [{"n_hi": n_hi[i], "block": blocks[i], "graphs": graphs[i], "in_lds": bool(lds[i])}
+                for i in range(k)]
 
     def __del__(self):
         h = getattr(self, "handle", None)
