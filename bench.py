@@ -191,9 +191,11 @@ def bench_closure(args):
     ER, mean degree 10, generated on the device), nv = 20.  Training labels are
     plain SLQ at m = 30 on the same probes; the closure sees the 5-step Gauss
     rule.  On held-out graphs every method's heat signature (256 t) is judged
-    against plain m = 30 (relative l2), and timed per graph end to end
-    (build, Lanczos, quadrature; for the closure also the network, the
-    bracket and the plain m = 30 fallback of flagged graphs)."""
+    against plain m = 30 (relative l2), and timed over the whole held-out set
+    end to end in batched runs (device union of the graphs, plan, Lanczos,
+    Gauss rules, quadrature; for the closure also the network, the bracket and
+    one batched plain m = 30 run over the flagged graphs): the median of three
+    timed passes after an untimed one."""
     import torch
     from paper_2003_01282_amd import closure as C
     from paper_2003_01282_amd import inputs
@@ -249,31 +251,41 @@ def bench_closure(args):
     ref = C.heat_from_q(dte.q_hi, dte.graph_n, nv).cpu().numpy()
     rows = {}
 
-    def time_plain(m):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        res = []
-        for i, g in enumerate(test_g):
-            a, b, s_ = C.lanczos_graph(g, nv, m, 7_000_000 + i)
-            th, w2 = S.ritz(a, b, s_)
-            res.append(S.signature(th, w2, C.graph_nodes(g), t))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        h = torch.stack(res).cpu().numpy()
-        return h, dt
+    def timed(fn, reps=3, name=""):
+        """fn() once untimed (first-use allocations), then the median of reps
+        timed runs; returns fn's last result and the median seconds."""
+        out = fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        log(f"{name} passes (s): {[round(x, 4) for x in ts]}")
+        return out, float(np.median(ts))
+
+    def plain(m):
+        # plain SLQ on every held-out graph in batched runs (union, plan, run)
+        return C.heat_batched(test_g, nv, m, t, 7_000_000).cpu().numpy()
 
     for m in (5, 6, 7, 8, 30):
-        h, dt = time_plain(m)
+        h, dt = timed(lambda: plain(m), name=f"plain m={m}")
         e = C.rel_l2(h, ref)
         rows[f"plain_m{m}"] = {"graphs_per_s": len(test_g) / dt, "rel_l2_median": float(np.median(e)),
                                "rel_l2_max": float(e.max()), "frac_le_1e-3": float(np.mean(e <= 1e-3))}
         log(f"plain m={m}: {rows[f'plain_m{m}']}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dinf = C.probe_data(test_g, nv=nv, t=t, seed=7_000_000, labels=False, mf=mf)
-    heat, flags = C.heat_with_fallback(net, dinf, test_g, nv=nv, t=t, seed=7_000_000, tol=gate_tol)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
+    def closure_pass():
+        t1 = time.perf_counter()
+        dinf = C.probe_data(test_g, nv=nv, t=t, seed=7_000_000, labels=False, mf=mf)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r = C.heat_with_fallback(net, dinf, test_g, nv=nv, t=t, seed=7_000_000, tol=gate_tol)
+        torch.cuda.synchronize()
+        log(f"closure pass: probe data {t2 - t1:.4f} s, network + bracket + fallback {time.perf_counter() - t2:.4f} s")
+        return r
+
+    (heat, flags), dt = timed(closure_pass, name="closure")
     e = C.rel_l2(heat, ref)
     rows["closure_m5"] = {"graphs_per_s": len(test_g) / dt, "rel_l2_median": float(np.median(e)),
                           "rel_l2_max": float(e.max()), "frac_le_1e-3": float(np.mean(e <= 1e-3)),

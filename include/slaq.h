@@ -242,23 +242,27 @@ slaq_status slaq_signature(const double* theta, const double* tau2, int nv, int 
 slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, int nv,
                       int m, double* out, void* stream);
 
-/* ---- Batched SLQ over many small graphs --------------------------------
+/* ---- Batched SLQ over many graphs -------------------------------------
  * A batch is the block-diagonal union of G graphs: node_off[g] .. node_off[g+1]
  * are graph g's nodes, row_ptr / col_idx its CSR rows with GLOBAL column ids
  * (each row's columns lie inside its own graph).  Graph g uses the probes of
  * slaq_lanczos with seed + g on that graph alone (keys are graph-local node
  * ids), so each output row equals the plain path on the graph by itself, up
  * to summation order.  Normalized Laplacian; nv <= 256; fewer than 2^31
- * nodes in the whole batch.  A bucket whose probe block (n_hi ceil(nv/4) 16
- * bytes) fits in 64 KB keeps it in LDS; larger graphs run the same
- * per-graph Lanczos with the probe blocks in a plan-owned global workspace
- * (up to 8 GB: slots of 3 n_hi ceil(nv/4) 16 + 4 n_hi bytes).
+ * nodes in the whole batch.  Graphs whose probe block (n ceil(nv/4) 16 bytes)
+ * fits in 64 KB are bucketed by node count and keep it in LDS; all larger
+ * graphs form one more bucket that runs the same per-graph Lanczos with the
+ * probe blocks in a global workspace: one slot of 3 n_max ceil(nv/4) 16 +
+ * 4 n_max bytes per workgroup its launch keeps resident, at most 16 GB
+ * (slaq_batch_workspace; the caller's via slaq_batch_set_workspace, else
+ * allocated by the first run and freed by slaq_batch_destroy).
  *
  * slaq_batch_plan (host): node_off and nnz_off are HOST copies of the node
  * offsets and of row_ptr at the graph starts (G+1 entries each);
  * node_off_dev / row_ptr / col_idx are the device arrays, which must stay
  * valid until slaq_batch_destroy.  Graphs are bucketed by node count
- * (<= 64, 128, 256, ...); bucket_blocks (optional, n_buckets_cfg entries)
+ * (<= 64, 128, 256, ... up to the LDS limit, then the global bucket);
+ * bucket_blocks (optional, n_buckets_cfg entries)
  * overrides each bucket's workgroup size; G nv m must stay below 2^31.  The
  * plan owns device memory until slaq_batch_destroy: the graph order, work
  * counters, and result buffers for whatever the caller does not ask for
@@ -295,6 +299,20 @@ slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, doubl
                            unsigned flags, void* stream);
 slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, double* vnge, int reps,
                                 int* blocks_out, float* best_ms_out, void* stream);
+/* Workspace of the global bucket: slaq_batch_workspace gives its size in
+ * bytes (0 when every graph runs in LDS); slaq_batch_set_workspace hands the
+ * plan caller-owned device memory of at least that size (256-byte aligned,
+ * valid for every later run; NULL returns to the plan's own), so that a
+ * caller who builds many plans can keep one buffer instead of allocating per
+ * plan.  A plan's runs use it in turn: runs that overlap on one workspace
+ * race. */
+slaq_status slaq_batch_workspace(slaq_batch_t b, size_t* bytes);
+slaq_status slaq_batch_set_workspace(slaq_batch_t b, void* workspace, size_t bytes);
+/* Per-graph probe seeds: with seeds (device uint64[G], caller-owned, valid for
+ * every later run) graph g uses the probes of slaq_lanczos with seeds[g]
+ * instead of seed + g; NULL restores seed + g.  Lets a batch of selected
+ * graphs reuse the probes they had in another batch. */
+slaq_status slaq_batch_set_seeds(slaq_batch_t b, const uint64_t* seeds);
 slaq_status slaq_batch_destroy(slaq_batch_t b);
 
 /* ---- Learned closure (an addition to the paper's method) ----------------

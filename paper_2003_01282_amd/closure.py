@@ -1,7 +1,8 @@
 """Learned-closure pipeline on top of the C ABI (control flow only; every
 numerical step runs in libslaq's kernels).
 
-Per graph the plain path runs m_hi Lanczos steps on nv probes; the first mf
+Per graph the batched engine (or the plain path, graph by graph) runs m_hi
+Lanczos steps on nv probes; the first mf
 coefficients of each probe give its mf-node Gauss rule (the closure's input)
 and its Gauss-Radau bracket, and the full m_hi-step rule gives the training
 label.  Inference needs only the mf-step run: y_hat = MLP(features), per-probe
@@ -37,21 +38,97 @@ def lanczos_graph(csr, nv, m, seed):
     return S.lanczos(g, nv, m, seed)
 
 
-def probe_data(graphs, nv, t, m_hi=30, mf=5, seed=0, labels=True):
-    """Runs the plain path per graph (graph i uses seed + i) and assembles the
+def _device_pair(csr):
+    return S.to_device(csr) if hasattr(csr, "row_ptr") else csr
+
+
+# nonzeros per batched run (bounds the union copy of the CSR: 4 bytes each);
+# every run ends on its largest graphs, so fewer, larger runs finish sooner
+BATCH_NNZ = 1 << 30
+
+
+# one workspace for the batched engine's global bucket per device, kept
+# across plans and grown as needed (a multi-GB allocation per plan would cost
+# more than the run itself on small batches)
+_WS = {}
+
+
+def _plan_workspace(b, device):
+    nbytes = b.workspace_bytes()
+    if nbytes == 0:
+        return
+    w = _WS.get(device)
+    if w is None or w.numel() < nbytes:
+        _WS.pop(device, None)
+        w = S._empty_aligned(nbytes, device)
+        _WS[device] = w
+    b.set_workspace(w)
+
+
+def _chunks(graphs):
+    """Consecutive index ranges whose total nonzeros stay under BATCH_NNZ."""
+    start, nnz = 0, 0
+    for i, g in enumerate(graphs):
+        k = int(g.nnz) if hasattr(g, "row_ptr") else int(g[1].numel())
+        if i > start and nnz + k > BATCH_NNZ:
+            yield start, i
+            start, nnz = i, 0
+        nnz += k
+    if start < len(graphs):
+        yield start, len(graphs)
+
+
+def lanczos_batched(graphs, nv, m, seed, seeds=None):
+    """alpha, beta [G nv][m] and steps [G nv] of every graph from the batched
+    engine, graph i with the probes of seed + i (or seeds[i])."""
+    A, B, St = [], [], []
+    for lo, hi in _chunks(graphs):
+        rp, ci, off = S.union_device([_device_pair(g) for g in graphs[lo:hi]])
+        b = S.batch_plan_device(rp, ci, off, nv, m, 0)
+        _plan_workspace(b, rp.device)
+        if seeds is not None:
+            b.set_seeds(torch.as_tensor(np.asarray(seeds[lo:hi], dtype=np.int64), device=rp.device))
+        o = S.batch_run(b, seed + lo, heat=False, vnge=False, coeffs=True)
+        A.append(o["alpha"].reshape(-1, m))
+        B.append(o["beta"].reshape(-1, m))
+        St.append(o["steps"].reshape(-1))
+    return torch.cat(A), torch.cat(B), torch.cat(St)
+
+
+def heat_batched(graphs, nv, m, t, seed, seeds=None):
+    """Plain SLQ heat signatures [G][nt] of every graph from the batched
+    engine (graph i with the probes of seed + i, or seeds[i])."""
+    out = []
+    for lo, hi in _chunks(graphs):
+        rp, ci, off = S.union_device([_device_pair(g) for g in graphs[lo:hi]])
+        b = S.batch_plan_device(rp, ci, off, nv, m, t.numel())
+        _plan_workspace(b, rp.device)
+        if seeds is not None:
+            b.set_seeds(torch.as_tensor(np.asarray(seeds[lo:hi], dtype=np.int64), device=rp.device))
+        out.append(S.batch_run(b, seed + lo, t, heat=True, vnge=False)["heat"])
+    return torch.cat(out)
+
+
+def probe_data(graphs, nv, t, m_hi=30, mf=5, seed=0, labels=True, batched=True):
+    """Runs SLQ on every graph (graph i uses seed + i) and assembles the
     closure's inputs (and labels when requested).  With labels=False only mf
     steps are run (step mf also yields beta_mf, the Radau bracket's coupling).
-    `graphs` holds host CSRs or (row_ptr, col_idx) device tensor pairs."""
+    `graphs` holds host CSRs or (row_ptr, col_idx) device tensor pairs;
+    batched=False runs the plain path graph by graph instead of the batched
+    engine (same probes, same results up to summation order)."""
     m = m_hi if labels else mf
-    A, B, St = [], [], []
-    for i, csr in enumerate(graphs):
-        a, b, s = lanczos_graph(csr, nv, m, seed + i)
-        A.append(a)
-        B.append(b)
-        St.append(s)
-    alpha = torch.cat(A)
-    beta = torch.cat(B)
-    steps = torch.cat(St)
+    if batched:
+        alpha, beta, steps = lanczos_batched(graphs, nv, m, seed)
+    else:
+        A, B, St = [], [], []
+        for i, csr in enumerate(graphs):
+            a, b, s = lanczos_graph(csr, nv, m, seed + i)
+            A.append(a)
+            B.append(b)
+            St.append(s)
+        alpha = torch.cat(A)
+        beta = torch.cat(B)
+        steps = torch.cat(St)
     th5, w5, thr, wr = S.closure_rules(alpha, beta, steps, mf=mf)
     x = S.closure_features(th5, w5)
     q5 = S.gauss_values(th5, w5, t)
@@ -98,16 +175,22 @@ def infer(net, data, tol=1e-3):
     return S.closure_apply(yhat, data.q5, data.qr, data.graph_n, data.nv, tol)
 
 
-def heat_with_fallback(net, data, graphs, nv, t, seed=0, tol=1e-3, m_plain=30):
+def heat_with_fallback(net, data, graphs, nv, t, seed=0, tol=1e-3, m_plain=30, batched=True):
     """Closure heat, with every flagged graph recomputed by plain SLQ
-    (m_plain steps, same probes: graph i uses seed + i).  Returns host arrays."""
+    (m_plain steps, same probes: graph i uses seed + i), in one batched run
+    (or graph by graph with batched=False).  Returns host arrays."""
     heat, flags = infer(net, data, tol)
     heat = heat.cpu().numpy()
     flags = flags.cpu().numpy()
-    for i in np.flatnonzero(flags):
-        a, b, s = lanczos_graph(graphs[i], nv, m_plain, seed + i)
-        th, w2 = S.ritz(a, b, s)
-        heat[i] = S.signature(th, w2, graph_nodes(graphs[i]), t).cpu().numpy()
+    idx = np.flatnonzero(flags)
+    if idx.size and batched:
+        sel = [graphs[i] for i in idx]
+        heat[idx] = heat_batched(sel, nv, m_plain, t, 0, seeds=seed + idx).cpu().numpy()
+    else:
+        for i in idx:
+            a, b, s = lanczos_graph(graphs[i], nv, m_plain, seed + i)
+            th, w2 = S.ritz(a, b, s)
+            heat[i] = S.signature(th, w2, graph_nodes(graphs[i]), t).cpu().numpy()
     return heat, flags
 
 

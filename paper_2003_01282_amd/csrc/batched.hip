@@ -48,6 +48,7 @@ struct BatchArgs {
     const int32_t* col;     // global column ids (device)
     int nv, m, n_max;
     uint64_t seed;
+    const uint64_t* seeds;  // [G] per-graph probe seeds, or NULL: seed + g
     double* alpha;          // [G][nv][m]
     double* beta;           // [G][nv][m]
     int32_t* steps;         // [G][nv]
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
         red[t] = (double)nonzero;
         // ---- probes R_1 = v (graph-local ids, seed + g), stored as X_1 = D^-1/2 v
         //      on rows with edges --------------------------------------------------
-        const uint64_t sg = a.seed + (uint64_t)g;
+        const uint64_t sg = a.seeds ? a.seeds[g] : a.seed + (uint64_t)g;
         for (int x = t; x < n * F; x += B) {
             const int i = x / F, qq = x % F, p0 = 4 * qq;
             const int64_t d = rp[i + 1] - rp[i];
@@ -369,7 +370,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
             nonzero += d > 0 ? 1 : 0;
         }
         red[t] = (double)nonzero;
-        const uint64_t sg = a.seed + (uint64_t)g;
+        const uint64_t sg = a.seeds ? a.seeds[g] : a.seed + (uint64_t)g;
         for (int64_t x = t; x < (int64_t)n * F; x += B) {
             const int i = (int)(x / F), qq = (int)(x % F), p0 = 4 * qq;
             const int64_t d = rp[i + 1] - rp[i];
@@ -554,8 +555,19 @@ typedef void (*BatchGlobalKernel)(BatchArgs, float4*, int64_t, float*, int64_t);
 // block this large would leave one workgroup per CU)
 constexpr size_t kLdsVecMax = 64 * 1024;
 // global workspace of a plan: slots of 3 n_hi F quads + n_hi floats, as many
-// as fit this budget (at most 8 per CU), for the largest global bucket
-constexpr size_t kGlobalWsBudget = size_t(8) << 30;
+// as fit this budget (at most 8 per CU)
+constexpr size_t kGlobalWsBudget = size_t(16) << 30;
+
+// Largest graph the LDS kernels serve for nv probes: the probe block within
+// kLdsVecMax, and rows per thread within the largest instantiation of each
+// workgroup size (pick_kernel: 32, 16, 8, 4 rows at 128, 256, 512, 1024).
+static int64_t lds_node_cap(int nv) {
+    const int F = (nv + 3) / 4;
+    static const int table[4][2] = {{128, 32}, {256, 16}, {512, 8}, {1024, 4}};
+    int64_t rows = 0;
+    for (const auto& e : table) rows = std::max<int64_t>(rows, (int64_t)(e[0] / F) * e[1]);
+    return std::min<int64_t>((int64_t)(kLdsVecMax / ((size_t)F * 16)), rows);
+}
 
 static BatchGlobalKernel pick_global(int block) {
     switch (block) {
@@ -596,14 +608,17 @@ struct slaq_batch_s {
     // alpha, beta, theta, tau2 [G][nv][m], steps [G][nv], tr L [G]
     double *al_dev, *be_dev, *th_dev, *w2_dev, *tr_dev;
     int32_t* st_dev;
-    // workspace of the global buckets (probe blocks and D^-1/2 per slot)
-    float4* gws;
-    float* gwsd;
+    // workspace of the global bucket (probe blocks, then D^-1/2, per slot):
+    // the caller's (slaq_batch_set_workspace) or allocated at the first run
     int64_t ws_quads, ws_floats;
+    size_t ws_bytes;
+    void* ws;
+    bool ws_owned;
     hipGraphExec_t exec;
     hipGraph_t graph;
     hipStream_t cap;  // private stream used only for capture (the NULL stream cannot be captured)
-    const void* exec_key[8];
+    const uint64_t* seeds;  // caller's per-graph seeds (device) or NULL
+    const void* exec_key[9];
     uint64_t exec_seed;
 };
 
@@ -616,8 +631,8 @@ static void free_plan(slaq_batch_s* b) {
     }
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (void* p : {(void*)b->order_dev, (void*)b->queues_dev, (void*)b->al_dev, (void*)b->be_dev,
-                    (void*)b->th_dev, (void*)b->w2_dev, (void*)b->st_dev, (void*)b->tr_dev, (void*)b->gws,
-                    (void*)b->gwsd})
+                    (void*)b->th_dev, (void*)b->w2_dev, (void*)b->st_dev, (void*)b->tr_dev,
+                    b->ws_owned ? b->ws : nullptr})
         if (p) (void)hipFree(p);
     delete b;
 }
@@ -700,8 +715,15 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
                  "a batch holds fewer than 2^31 nodes in all (column ids are int32)");
     SLAQ_REQUIRE(n_graphs * nv * m <= INT32_MAX, SLAQ_ERR_UNSUPPORTED,
                  "G * nv * m must stay below 2^31 (got %lld)", (long long)(n_graphs * nv * m));
-    std::vector<int64_t> edges = {0, 64};
-    while (edges.back() < nmax) edges.push_back(edges.back() * 2);
+    // LDS buckets by doubling node counts up to the largest probe block that
+    // stays in LDS, then one global bucket for every larger graph (a single
+    // persistent launch pulling them largest first keeps the CUs busy where
+    // size classes of their own would each leave most of the chip idle)
+    const int64_t lds_cap_n = lds_node_cap(nv);
+    std::vector<int64_t> edges = {0, std::min<int64_t>(64, lds_cap_n)};
+    while (edges.back() < nmax && edges.back() < lds_cap_n)
+        edges.push_back(std::min<int64_t>(edges.back() * 2, lds_cap_n));
+    if (edges.back() < nmax) edges.push_back(nmax);
     slaq_batch_s* b = new (std::nothrow) slaq_batch_s();
     SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "out of host memory");
     b->G = n_graphs;
@@ -734,21 +756,30 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         for (auto& pr : members[k]) top = std::max<int64_t>(top, node_off[pr.second + 1] - node_off[pr.second]);
         c.n_hi = (int)top;
         const int Fq = (nv + 3) / 4;
-        c.global = (size_t)c.n_hi * Fq * 16 > kLdsVecMax;
-        if (c.global) {
-            const size_t slot_bytes = (size_t)3 * c.n_hi * Fq * 16 + (size_t)c.n_hi * 4;
+        c.global = c.n_hi > lds_cap_n;
+        const size_t slot_bytes = (size_t)3 * c.n_hi * Fq * 16 + (size_t)c.n_hi * 4;
+        if (c.global)
             c.slots = (int)std::max<size_t>(1, std::min<size_t>(kGlobalWsBudget / slot_bytes,
                                                                 (size_t)device_cus() * 8));
-            b->ws_quads = std::max<int64_t>(b->ws_quads, (int64_t)c.slots * 3 * c.n_hi * Fq);
-            b->ws_floats = std::max<int64_t>(b->ws_floats, (int64_t)c.slots * c.n_hi);
-        }
         const int bidx = (int)b->buckets.size();
-        int block = c.n_hi <= 64 ? 128 : (c.n_hi <= 256 ? 256 : 512);
+        // defaults (slaq_batch_autotune refines them); a global bucket is led by
+        // its largest graphs, each on one workgroup: the widest one finishes
+        // them soonest (1024 threads: 80 ms against 97 at 512 for 2,000 graphs
+        // of 1e3 to 1e5 nodes, nv = 20, m = 5)
+        int block = c.global ? 1024 : (c.n_hi <= 64 ? 128 : (c.n_hi <= 256 ? 256 : 512));
         if (bucket_blocks && bidx < n_buckets_cfg && bucket_blocks[bidx] > 0) block = bucket_blocks[bidx];
         slaq_status s = configure_bucket(c, nv, m, block);
         if (s != SLAQ_OK) {
             delete b;
             return s;
+        }
+        if (c.global) {
+            // one slot per workgroup the chosen block keeps resident (the
+            // autotuner's other sizes are capped to as many)
+            c.slots = std::min(c.slots, c.grid);
+            b->ws_quads = (int64_t)c.slots * 3 * c.n_hi * Fq;
+            b->ws_floats = (int64_t)c.slots * c.n_hi;
+            b->ws_bytes = align_up((size_t)b->ws_quads * 16, 256) + align_up((size_t)b->ws_floats * 4, 256);
         }
         b->bucket_start.push_back((int)order.size());
         std::vector<int32_t> ids;
@@ -766,9 +797,7 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         hipMalloc(&b->al_dev, coeffs) != hipSuccess || hipMalloc(&b->be_dev, coeffs) != hipSuccess ||
         hipMalloc(&b->th_dev, coeffs) != hipSuccess || hipMalloc(&b->w2_dev, coeffs) != hipSuccess ||
         hipMalloc(&b->st_dev, (size_t)n_graphs * nv * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&b->tr_dev, (size_t)n_graphs * sizeof(double)) != hipSuccess ||
-        (b->ws_quads > 0 && hipMalloc(&b->gws, (size_t)b->ws_quads * sizeof(float4)) != hipSuccess) ||
-        (b->ws_floats > 0 && hipMalloc(&b->gwsd, (size_t)b->ws_floats * sizeof(float)) != hipSuccess)) {
+        hipMalloc(&b->tr_dev, (size_t)n_graphs * sizeof(double)) != hipSuccess) {
         free_plan(b);
         set_error("hipMalloc of the batch plan failed");
         return SLAQ_ERR_HIP;
@@ -795,6 +824,15 @@ slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* b
     return SLAQ_OK;
 }
 
+// the global bucket's workspace: allocated here at the first run unless the
+// caller gave one (never while a stream is being captured)
+static slaq_status ensure_workspace(slaq_batch_t b) {
+    if (b->ws_bytes == 0 || b->ws) return SLAQ_OK;
+    SLAQ_HIP(hipMalloc(&b->ws, b->ws_bytes));
+    b->ws_owned = true;
+    return SLAQ_OK;
+}
+
 static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t, double* heat, double* vnge,
                                  double* alpha, double* beta, int32_t* steps, double* theta, double* tau2,
                                  hipStream_t st, int only_bucket) {
@@ -818,6 +856,7 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
         a.m = b->m;
         a.n_max = c.n_hi;
         a.seed = seed;
+        a.seeds = b->seeds;
         a.alpha = al;
         a.beta = be;
         a.steps = sp;
@@ -826,9 +865,12 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
         if (c.global) {
             const int Fq = (b->nv + 3) / 4;
             BatchGlobalKernel kern = pick_global(c.block);
+            SLAQ_REQUIRE(b->ws, SLAQ_ERR_WORKSPACE, "the batch plan has no workspace");
+            float4* gws = (float4*)b->ws;
+            float* gwsd = (float*)((char*)b->ws + align_up((size_t)b->ws_quads * 16, 256));
             SLAQ_TIMED("batch_slq", st,
-                       hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a, b->gws,
-                                          (int64_t)c.n_hi * Fq, b->gwsd, (int64_t)c.n_hi));
+                       hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a, gws,
+                                          (int64_t)c.n_hi * Fq, gwsd, (int64_t)c.n_hi));
         } else {
             BatchKernel kern = pick_kernel(c.block, c.ipt);
             SLAQ_TIMED("batch_slq", st, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a));
@@ -857,9 +899,10 @@ slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, doubl
     SLAQ_REQUIRE(!heat || (t && b->nt > 0), SLAQ_ERR_INVALID_ARG, "heat needs the time grid t (nt > 0)");
     SLAQ_REQUIRE((!beta || alpha) && (!tau2 || theta), SLAQ_ERR_INVALID_ARG, "beta needs alpha, tau2 needs theta");
     hipStream_t st = (hipStream_t)stream;
+    SLAQ_TRY(ensure_workspace(b));
     if (!(flags & SLAQ_BATCH_GRAPH)) return enqueue_batch(b, seed, t, heat, vnge, alpha, beta, steps, theta, tau2, st, -1);
     // replay one captured hipGraph; (re)capture when the buffers or the seed change
-    const void* key[8] = {t, heat, vnge, alpha, beta, steps, theta, tau2};
+    const void* key[9] = {t, heat, vnge, alpha, beta, steps, theta, tau2, b->seeds};
     const bool same = b->exec && std::memcmp(key, b->exec_key, sizeof(key)) == 0 && b->exec_seed == seed;
     if (!same) {
         if (b->exec) {
@@ -892,6 +935,7 @@ slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, d
     SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
     SLAQ_REQUIRE(reps >= 1 && reps <= 100, SLAQ_ERR_INVALID_ARG, "reps must be in [1, 100]");
     hipStream_t st = (hipStream_t)stream;
+    SLAQ_TRY(ensure_workspace(b));
     const int cand[4] = {128, 256, 512, 1024};
     hipEvent_t e0, e1;
     SLAQ_HIP(hipEventCreate(&e0));
@@ -938,6 +982,39 @@ slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, d
         (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
     }
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_workspace(slaq_batch_t b, size_t* bytes) {
+    clear_error();
+    SLAQ_REQUIRE(b && bytes, SLAQ_ERR_INVALID_ARG, "NULL argument");
+    *bytes = b->ws_bytes;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_set_workspace(slaq_batch_t b, void* workspace, size_t bytes) {
+    clear_error();
+    SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
+    SLAQ_REQUIRE(!workspace || bytes >= b->ws_bytes, SLAQ_ERR_WORKSPACE,
+                 "batch workspace needs %zu bytes, got %zu", b->ws_bytes, bytes);
+    SLAQ_REQUIRE(((uintptr_t)workspace & 255) == 0, SLAQ_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (b->ws_owned) {
+        SLAQ_HIP(hipFree(b->ws));
+        b->ws_owned = false;
+    }
+    b->ws = b->ws_bytes ? workspace : nullptr;
+    if (b->exec) {  // launches captured with the old workspace
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+    }
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_set_seeds(slaq_batch_t b, const uint64_t* seeds) {
+    clear_error();
+    SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
+    b->seeds = seeds;
     return SLAQ_OK;
 }
 

@@ -26,6 +26,7 @@ SLAQ_CV_TAYLOR = 1
 SLAQ_CV_FITTED = 2
 SLAQ_MAX_PROBES = 4096
 SLAQ_MAX_STEPS = 64
+SLAQ_ERR_INVALID_ARG = 1
 
 STATUS = {
     0: "SLAQ_OK", 1: "SLAQ_ERR_INVALID_ARG", 2: "SLAQ_ERR_NOT_SYMMETRIC", 3: "SLAQ_ERR_NUMERIC",
@@ -62,6 +63,9 @@ SIGNATURES = {
     "slaq_batch_plan": [_i64, _vp, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _int, ctypes.POINTER(_vp)],
     "slaq_batch_buckets": [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp],
     "slaq_batch_run": [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
+    "slaq_batch_set_seeds": [_vp, _vp],
+    "slaq_batch_workspace": [_vp, ctypes.POINTER(_sz)],
+    "slaq_batch_set_workspace": [_vp, _vp, _sz],
     "slaq_batch_autotune": [_vp, _vp, _vp, _vp, _int, _vp, _vp, _vp],
     "slaq_batch_destroy": [_vp],
     "slaq_closure_create": [_int, _int, _int, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)],
@@ -324,7 +328,7 @@ SLAQ_BATCH_GRAPH = 1
 
 
 class Batch:
-    """Plan of a batch of small graphs (slaq_batch_plan); keeps the device CSR
+    """Plan of a batch of graphs (slaq_batch_plan); keeps the device CSR
     alive and owns the library plan."""
 
     def __init__(self, handle, n_graphs, nv, m, nt, keep):
@@ -332,6 +336,29 @@ class Batch:
         self.G = n_graphs
         self.nv, self.m, self.nt = nv, m, nt
         self._keep = keep
+
+    def workspace_bytes(self):
+        """slaq_batch_workspace: bytes the global bucket needs (0 if none)."""
+        n = _sz()
+        _check(lib().slaq_batch_workspace(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def set_workspace(self, ws):
+        """slaq_batch_set_workspace with a caller-owned device buffer (a
+        256-byte aligned tensor, e.g. from _empty_aligned) or None."""
+        self._keep["workspace"] = ws
+        nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+        _check(lib().slaq_batch_set_workspace(self.handle, _ptr(ws), nbytes))
+
+    def set_seeds(self, seeds):
+        """slaq_batch_set_seeds: per-graph probe seeds (uint64-valued int64
+        device tensor [G]) or None for seed + g."""
+        if seeds is not None:
+            _dev(seeds, torch.int64, "seeds")
+            if seeds.numel() != self.G:
+                raise SlaqError(SLAQ_ERR_INVALID_ARG, f"seeds needs {self.G} entries")
+        self._keep["seeds"] = seeds
+        _check(lib().slaq_batch_set_seeds(self.handle, _ptr(seeds)))
 
     def buckets(self):
         nb = _int()
@@ -367,6 +394,49 @@ def batch_plan(union_csr, node_off, nv, m, nt, bucket_blocks=None, device="cuda"
     _check(lib().slaq_batch_plan(G, node_off.ctypes.data_as(_vp), nnz_off.ctypes.data_as(_vp), _ptr(goff),
                                  _ptr(rp), _ptr(ci), nv, m, nt, bb, nbb, ctypes.byref(h)))
     return Batch(h, G, nv, m, nt, {"rp": rp, "ci": ci, "goff": goff})
+
+
+def batch_plan_device(row_ptr, col_idx, node_off, nv, m, nt, bucket_blocks=None):
+    """slaq_batch_plan for a block-diagonal union already on the device
+    (int64 row_ptr, int32 global col_idx; host int64 node offsets [G+1])."""
+    import numpy as np
+    _dev(row_ptr, torch.int64, "row_ptr")
+    _dev(col_idx, torch.int32, "col_idx")
+    node_off = np.ascontiguousarray(node_off, dtype=np.int64)
+    dev = row_ptr.device
+    goff = torch.from_numpy(node_off).to(dev)
+    nnz_off = np.ascontiguousarray(row_ptr[goff].cpu().numpy(), dtype=np.int64)
+    G = len(node_off) - 1
+    bb = None
+    nbb = 0
+    if bucket_blocks is not None:
+        bb = (ctypes.c_int * len(bucket_blocks))(*bucket_blocks)
+        nbb = len(bucket_blocks)
+    h = _vp()
+    _check(lib().slaq_batch_plan(G, node_off.ctypes.data_as(_vp), nnz_off.ctypes.data_as(_vp), _ptr(goff),
+                                 _ptr(row_ptr), _ptr(col_idx), nv, m, nt, bb, nbb, ctypes.byref(h)))
+    return Batch(h, G, nv, m, nt, {"rp": row_ptr, "ci": col_idx, "goff": goff})
+
+
+def union_device(graphs):
+    """Block-diagonal union of device CSRs [(row_ptr, col_idx), ...] ->
+    (row_ptr, col_idx with global ids, host node offsets [G+1])."""
+    import numpy as np
+    rps = [g[0] for g in graphs]
+    cis = [g[1] for g in graphs]
+    dev = rps[0].device
+    n = np.array([rp.numel() - 1 for rp in rps], dtype=np.int64)
+    nnz = np.array([ci.numel() for ci in cis], dtype=np.int64)
+    node_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    nnz_off = np.concatenate([[0], np.cumsum(nnz)]).astype(np.int64)
+    if node_off[-1] > 2**31 - 1:
+        raise SlaqError(SLAQ_ERR_INVALID_ARG, "a union needs fewer than 2^31 nodes")
+    shift_c = torch.repeat_interleave(torch.from_numpy(node_off[:-1]).to(dev), torch.from_numpy(nnz).to(dev))
+    ci = (torch.cat(cis).to(torch.int64) + shift_c).to(torch.int32)
+    shift_r = torch.repeat_interleave(torch.from_numpy(nnz_off[:-1]).to(dev), torch.from_numpy(n).to(dev))
+    rp = torch.cat([torch.cat([r[:-1] for r in rps]) + shift_r,
+                    torch.tensor([int(nnz_off[-1])], dtype=torch.int64, device=dev)])
+    return rp, ci, node_off
 
 
 def batch_run(b, seed, t=None, heat=True, vnge=True, ritz=False, coeffs=False, graph=False, out=None,

@@ -88,3 +88,22 @@ def test_global_buckets_graph_replay_and_autotune():
     print(choice, b.buckets(), flush=True)
     after = S.batch_run(b, 3, t)["heat"].cpu().numpy()
     np.testing.assert_allclose(after, ref, rtol=1e-6)
+
+
+def test_caller_workspace():
+    print("\n[gpu] batched global bucket: caller-owned workspace", flush=True)
+    gs = mixed(13)
+    union, off = inputs.disjoint_union(gs)
+    t = torch.from_numpy(T).cuda()
+    b = S.batch_plan(union, off, nv=20, m=6, nt=T.size)
+    need = b.workspace_bytes()
+    assert need > 0
+    own = S.batch_run(b, 21, t)["heat"].cpu().numpy()
+    with pytest.raises(S.SlaqError):
+        b.set_workspace(S._empty_aligned(need // 2, "cuda"))
+    b.set_workspace(S._empty_aligned(need, "cuda"))
+    np.testing.assert_array_equal(S.batch_run(b, 21, t)["heat"].cpu().numpy(), own)
+    # small graphs only: no global bucket, no workspace
+    small = inputs.small_graph_mix(20, seed=4)
+    u2, o2 = inputs.disjoint_union(small)
+    assert S.batch_plan(u2, o2, nv=20, m=6, nt=T.size).workspace_bytes() == 0

@@ -128,14 +128,18 @@ def test_closure_gain_over_plain_five_steps(trained):
 def test_forced_fallback_reproduces_plain(trained):
     net, dtr, dte, hist, test_g = trained
     tt = torch.from_numpy(T).cuda()
-    # a negative tolerance rejects every prediction: every graph falls back
-    heat, flags = C.heat_with_fallback(net, dte, test_g, nv=20, t=tt, seed=900, tol=-1.0)
-    assert int(flags.sum()) == len(test_g)
+    # a negative tolerance rejects every prediction: every graph falls back,
+    # graph by graph (the plain path itself) or in one batched run with the
+    # graphs' own probe seeds (the same rule up to summation order)
+    heat, flags = C.heat_with_fallback(net, dte, test_g, nv=20, t=tt, seed=900, tol=-1.0, batched=False)
+    heat_b, flags_b = C.heat_with_fallback(net, dte, test_g, nv=20, t=tt, seed=900, tol=-1.0)
+    assert int(flags.sum()) == len(test_g) and np.array_equal(flags, flags_b)
     for i in (0, 7, 19):
         a, b, s = C.lanczos_graph(test_g[i], 20, 30, 900 + i)
         th, w2 = S.ritz(a, b, s)
         plain = S.signature(th, w2, test_g[i].n, tt).cpu().numpy()
         assert np.array_equal(heat[i], plain)
+        np.testing.assert_allclose(heat_b[i], plain, rtol=1e-4)
     # with the normal tolerance only flagged graphs are recomputed
     heat2, flags2 = C.heat_with_fallback(net, dte, test_g, nv=20, t=tt, seed=900, tol=1e-3)
     h_clo, _ = C.infer(net, dte, tol=1e-3)
@@ -143,3 +147,14 @@ def test_forced_fallback_reproduces_plain(trained):
     for i in range(len(test_g)):
         if not flags2[i]:
             assert np.array_equal(heat2[i], h_clo[i])
+
+
+def test_batched_probe_data_matches_graph_by_graph():
+    tt = torch.from_numpy(T).cuda()
+    gs = closure_graphs(12, seed=5)
+    d_b = C.probe_data(gs, nv=20, t=tt, seed=40)
+    d_p = C.probe_data(gs, nv=20, t=tt, seed=40, batched=False)
+    # two FP32 runs of the same recurrence in different summation orders
+    for name in ("q5", "q_hi", "qr"):
+        a, b = getattr(d_b, name).cpu().numpy(), getattr(d_p, name).cpu().numpy()
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-9, err_msg=name)
