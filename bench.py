@@ -375,6 +375,8 @@ def main():
     ap.add_argument("--closure-epochs", type=int, default=12)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (calibrates hardware byte counters)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of one step captured into a HIP graph (launch-bound workloads)")
     ap.add_argument("--permute", action="store_true",
                     help="rename the nodes of a host-generated graph by a seeded random permutation first")
     ap.add_argument("--line-probe", action="store_true",
@@ -465,13 +467,28 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    run = step
     S.profile_reset()
     S.profile_enable(True)
-    log(f"timing {args.steps} steps")
+    if args.graph:
+        # one step captured into a HIP graph (the library launches on the
+        # current stream, torch's capture stream here) and replayed; the stage
+        # timings come from as many eager steps, run first
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        S.profile_enable(False)
+        hg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(hg):
+            step()
+        hg.replay()
+        torch.cuda.synchronize()
+        run = hg.replay
+    log(f"timing {args.steps} steps{' (graph replays)' if args.graph else ''}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     S.profile_enable(False)
@@ -547,7 +564,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}_slq", "n": n, "nnz": nnz, "nv": nv, "m": m,
                    "nt": nt, "outputs": ["heat", "wave", "vnge"], "laplacian": "normalized",
-                   "generator": spec, "permuted": args.permute, "n_nonisolated": n_act,
+                   "generator": spec, "permuted": args.permute, "hipgraph": args.graph, "n_nonisolated": n_act,
                    "relabeled": graphs[0].relabeled(), "schedule": graphs[0].schedule(),
                    "tile_quads": args.tile},
         "roofline": {"bound": "hbm", "kernel": "spmm_pieces+spmm_rows+spmm_heavy", "achieved": achieved,
