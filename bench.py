@@ -80,7 +80,7 @@ def measured_traffic(args):
     rec = json.load(open(TRAFFIC_RECORD))
     if rec.get("digest") != kernel_sources_digest():
         return None
-    return rec["bytes_per_launch"]
+    return rec
 
 
 def cpu_baseline(csr, nv, m, seed, budget_s=25.0):
@@ -508,7 +508,11 @@ def main():
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
     upd_ms = stages["update"]["avg_ms"]
     upd_gbs = update_algorithmic_bytes(n, n_act, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
-    traffic = measured_traffic(args)
+    rec = measured_traffic(args)
+    traffic = rec["bytes_per_launch"] if rec else None
+    upd_traffic = rec.get("update_bytes_per_launch") if rec else None
+    # the Lanczos loop alone (SpMM stage, update, finalizes) per step
+    loop_ms = sum(stages[k]["ms_per_step"] for k in ("spmm_pieces", "spmm_rows", "spmm_heavy", "finalize", "update"))
 
     # the variance-reduced estimate (control variates tr L, tr L^2; fitted
     # coefficients), timed once after the timed region: it is not part of the
@@ -574,6 +578,10 @@ def main():
                      "amplification": traffic / spmm_bytes if traffic else None},
         "spmm_hbm_gbs": achieved,
         "update_gbs": upd_gbs,
+        "update_traffic": {"bytes_per_launch": upd_traffic,
+                           "gbs": upd_traffic / (upd_ms * 1e-3) / 1e9 if upd_traffic and upd_ms else None},
+        "lanczos_loop": {"ms_per_step": loop_ms,
+                         "nnz_probes_steps_per_s": nnz * nv * m / (loop_ms * 1e-3) if loop_ms else None},
         "stages": stages,
         "heat_sane": sanity,
         "variance_reduction": vr,

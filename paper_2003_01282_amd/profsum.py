@@ -24,6 +24,7 @@ from collections import defaultdict
 from pathlib import Path
 
 SPMM_STAGE = ("spmm_pieces", "spmm_rows", "spmm_heavy")
+UPDATE_KERNEL = "update"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 KERNEL_SOURCES = ("common.hpp", "graph.hip", "relabel.hip", "lanczos.hip")
 
@@ -83,13 +84,16 @@ def traffic(fetch_dir, write_dir, copy_bytes, out_json):
         copy = _find(t, COPY_KERNEL)[counter]
         scale = copy_bytes / (sum(copy) * 1024.0)  # true bytes per counted byte
         rec[f"{counter}_scale"] = scale
-        for k in SPMM_STAGE:
+        for k in SPMM_STAGE + (UPDATE_KERNEL,):
             v = _find(t, f"slaq::{k}")[counter]
             kib = sum(v) / len(v)
             rec["kernels"].setdefault(k, {})[counter + "_KiB"] = kib
             rec["kernels"][k][counter + "_bytes"] = kib * 1024.0 * scale
-            per_launch += kib * 1024.0 * scale
-    rec["bytes_per_launch"] = per_launch
+            if k in SPMM_STAGE:
+                per_launch += kib * 1024.0 * scale
+    rec["bytes_per_launch"] = per_launch  # the SpMM stage
+    rec["update_bytes_per_launch"] = sum(rec["kernels"][UPDATE_KERNEL].get(c + "_bytes", 0.0)
+                                         for c in ("FETCH_SIZE", "WRITE_SIZE"))
     Path(out_json).write_text(json.dumps(rec, indent=1) + "\n")
     print(json.dumps(rec, indent=1))
 
