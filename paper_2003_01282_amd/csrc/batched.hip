@@ -617,6 +617,11 @@ struct slaq_batch_s {
     hipGraphExec_t exec;
     hipGraph_t graph;
     hipStream_t cap;  // private stream used only for capture (the NULL stream cannot be captured)
+    // side streams and events: the buckets of a run are launched concurrently
+    // (bucket k > 0 on side[k - 1], forked from and joined to the caller's stream)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork;
     const uint64_t* seeds;  // caller's per-graph seeds (device) or NULL
     const void* exec_key[9];
     uint64_t exec_seed;
@@ -630,6 +635,9 @@ static void free_plan(slaq_batch_s* b) {
         (void)hipGraphDestroy(b->graph);
     }
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipStream_t x : b->side) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     for (void* p : {(void*)b->order_dev, (void*)b->queues_dev, (void*)b->al_dev, (void*)b->be_dev,
                     (void*)b->th_dev, (void*)b->w2_dev, (void*)b->st_dev, (void*)b->tr_dev,
                     b->ws_owned ? b->ws : nullptr})
@@ -824,9 +832,21 @@ slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* b
     return SLAQ_OK;
 }
 
-// the global bucket's workspace: allocated here at the first run unless the
-// caller gave one (never while a stream is being captured)
+// the global bucket's workspace (allocated here at the first run unless the
+// caller gave one) and the side streams of the bucket launches; never while a
+// stream is being captured
 static slaq_status ensure_workspace(slaq_batch_t b) {
+    if (b->side.empty() && b->buckets.size() > 1) {
+        SLAQ_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (size_t k = 1; k < b->buckets.size(); ++k) {
+            hipStream_t x = nullptr;
+            hipEvent_t e = nullptr;
+            SLAQ_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+            b->side.push_back(x);
+            SLAQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->joins.push_back(e);
+        }
+    }
     if (b->ws_bytes == 0 || b->ws) return SLAQ_OK;
     SLAQ_HIP(hipMalloc(&b->ws, b->ws_bytes));
     b->ws_owned = true;
@@ -842,9 +862,18 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
     int32_t* sp = steps ? steps : b->st_dev;
     hipLaunchKernelGGL(reset_queues, dim3(1), dim3(64), 0, st, b->queues_dev, nbk);
     SLAQ_LAUNCHED();
+    // every bucket of a full run on a stream of its own: their persistent grids
+    // fill one another's tails
+    const bool fan = only_bucket < 0 && nbk > 1 && (int)b->side.size() == nbk - 1;
+    if (fan) SLAQ_HIP(hipEventRecord(b->fork, st));
     for (int k = 0; k < nbk; ++k) {
         if (only_bucket >= 0 && k != only_bucket) continue;
         const BucketCfg& c = b->buckets[k];
+        hipStream_t bs = st;
+        if (fan && k > 0) {
+            bs = b->side[k - 1];
+            SLAQ_HIP(hipStreamWaitEvent(bs, b->fork, 0));
+        }
         BatchArgs a{};
         a.order = b->order_dev + b->bucket_start[k];
         a.count = b->bucket_start[k + 1] - b->bucket_start[k];
@@ -868,14 +897,18 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
             SLAQ_REQUIRE(b->ws, SLAQ_ERR_WORKSPACE, "the batch plan has no workspace");
             float4* gws = (float4*)b->ws;
             float* gwsd = (float*)((char*)b->ws + align_up((size_t)b->ws_quads * 16, 256));
-            SLAQ_TIMED("batch_slq", st,
-                       hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a, gws,
+            SLAQ_TIMED("batch_slq", bs,
+                       hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, bs, a, gws,
                                           (int64_t)c.n_hi * Fq, gwsd, (int64_t)c.n_hi));
         } else {
             BatchKernel kern = pick_kernel(c.block, c.ipt);
-            SLAQ_TIMED("batch_slq", st, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, st, a));
+            SLAQ_TIMED("batch_slq", bs, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, bs, a));
         }
         SLAQ_LAUNCHED();
+        if (fan && k > 0) {
+            SLAQ_HIP(hipEventRecord(b->joins[k - 1], bs));
+            SLAQ_HIP(hipStreamWaitEvent(st, b->joins[k - 1], 0));
+        }
     }
     if (only_bucket >= 0) return SLAQ_OK;  // autotuner trial: the Lanczos part of one bucket
     if (!(heat || vnge || theta)) return SLAQ_OK;
