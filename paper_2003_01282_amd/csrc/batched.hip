@@ -1,5 +1,5 @@
-// Batched SLQ for many small graphs (paper §3.1 and Algorithm 1 applied to
-// every graph of a collection).  One workgroup runs the Lanczos part of one
+// Batched SLQ for many graphs (paper §3.1 and Algorithm 1 applied to every
+// graph of a collection).  One workgroup runs the Lanczos part of one
 // whole graph - degrees, probes, m steps - with the current Lanczos vector in
 // LDS and the previous one and w in registers, and writes alpha, beta, the
 // step counts and tr L.  As in the plain path the vectors of rows with edges
@@ -46,7 +46,7 @@ struct BatchArgs {
     const int64_t* goff;    // node offsets [G+1] (device)
     const int64_t* rp;      // global row_ptr (device)
     const int32_t* col;     // global column ids (device)
-    int nv, m, n_max;
+    int nv, m, n_max;       // n_max: node count the LDS layout is sized for
     uint64_t seed;
     const uint64_t* seeds;  // [G] per-graph probe seeds, or NULL: seed + g
     double* alpha;          // [G][nv][m]
@@ -652,8 +652,7 @@ static int device_cus() {
     return cus > 0 ? cus : 256;
 }
 
-static slaq_status configure_bucket(BucketCfg& b, int nv, int m, int block) {
-    (void)m;
+static slaq_status configure_bucket(BucketCfg& b, int nv, int block) {
     const int F = (nv + 3) / 4;
     const int bact = (block / F) * F;
     SLAQ_REQUIRE(bact >= F && bact >= nv, SLAQ_ERR_UNSUPPORTED, "block %d too small for nv=%d", block, nv);
@@ -776,7 +775,7 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         // of 1e3 to 1e5 nodes, nv = 20, m = 5)
         int block = c.global ? 1024 : (c.n_hi <= 64 ? 128 : (c.n_hi <= 256 ? 256 : 512));
         if (bucket_blocks && bidx < n_buckets_cfg && bucket_blocks[bidx] > 0) block = bucket_blocks[bidx];
-        slaq_status s = configure_bucket(c, nv, m, block);
+        slaq_status s = configure_bucket(c, nv, block);
         if (s != SLAQ_OK) {
             delete b;
             return s;
@@ -978,7 +977,7 @@ slaq_status slaq_batch_autotune(slaq_batch_t b, const double* t, double* heat, d
         float best_ms = 1e30f;
         for (int ci = 0; ci < 4; ++ci) {
             BucketCfg c = b->buckets[k];
-            if (configure_bucket(c, b->nv, b->m, cand[ci]) != SLAQ_OK) continue;
+            if (configure_bucket(c, b->nv, cand[ci]) != SLAQ_OK) continue;
             const BucketCfg keep = b->buckets[k];
             b->buckets[k] = c;
             std::vector<float> ts;
