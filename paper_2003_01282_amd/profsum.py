@@ -53,6 +53,21 @@ def stats(d, out=sys.stdout):
               f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}", file=out)
 
 
+def calls(d, stem, out=sys.stdout):
+    """Every launch of the kernels whose name contains `stem`, in trace order:
+    grid, workgroup size and duration (from the kernel trace)."""
+    f = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0]
+    print(f"{'#':>5s} {'kernel':48s} {'grid':>10s} {'wg':>5s} {'ms':>10s}", file=out)
+    k = 0
+    for r in csv.DictReader(open(f)):
+        if stem not in r["Kernel_Name"]:
+            continue
+        ms = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        print(f"{k:5d} {short(r['Kernel_Name'])[:48]:48s} {int(r['Grid_Size_X']):10d} "
+              f"{int(r['Workgroup_Size_X']):5d} {ms:10.3f}", file=out)
+        k += 1
+
+
 def pmc_table(d):
     """{kernel: {counter: [per-dispatch values]}} over every counter file under d."""
     acc = defaultdict(lambda: defaultdict(list))
@@ -104,6 +119,8 @@ if __name__ == "__main__":
         stats(sys.argv[2])
     elif cmd == "pmc":
         pmc(sys.argv[2])
+    elif cmd == "calls":
+        calls(sys.argv[2], sys.argv[3])
     elif cmd == "traffic":
         traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5])
     else:
