@@ -2,6 +2,7 @@
 
     python -m paper_2003_01282_amd.profsum stats <dir>      # --kernel-trace --stats
     python -m paper_2003_01282_amd.profsum pmc <dir>        # --pmc runs
+    python -m paper_2003_01282_amd.profsum calls <dir> <name>   # every launch of a kernel (--kernel-trace)
     python -m paper_2003_01282_amd.profsum traffic <fetch_dir> <write_dir> <copy_bytes> <out.json>
 
 `stats` prints calls and average/total duration per kernel from
