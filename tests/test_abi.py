@@ -50,3 +50,21 @@ def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
         S.build_graph(torch.zeros(3, dtype=torch.int64), torch.zeros(2, dtype=torch.int32))
+
+
+def test_missing_library_fails_loudly():
+    # no fallback path: without libslaq.so every entry point raises
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from pathlib import Path\n"
+            "from paper_2003_01282_amd import slaq as S\n"
+            "S.LIB_PATH = Path('/nonexistent/libslaq.so')\n"
+            "try:\n"
+            "    S.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "    sys.exit(0)\n"
+            "sys.exit(3)\n") % str(HEADER.parents[1])
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "is missing" in r.stdout, (r.stdout, r.stderr)
