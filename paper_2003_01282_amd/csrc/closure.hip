@@ -9,6 +9,7 @@
 // Network: d_in (padded to 32) -> 256 -> 256 -> 256 -> nt, SiLU between,
 // MSE loss, Adam on FP32 master weights; every product runs on BF16 MFMA
 // (v_mfma_f32_16x16x32_bf16) with FP32 accumulation.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -41,6 +42,8 @@ struct GemmArgs {
     float* Z;        // EPI_BIAS_SILU: pre-activation out
     bf16* H;         // EPI_BIAS_SILU: activation out; EPI_DSILU: gradient out
     const float* Zin;  // EPI_DSILU: pre-activation in
+    int kslice;        // split K: rows of K per blockIdx.z (0: the whole of K)
+    float* part;       // split K: FP32 partial products [gridDim.z][M][ldc]
 };
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
@@ -52,7 +55,9 @@ __device__ __forceinline__ float dsilu_f(float z) {
 // C (M x N) = op(A) (M x K) * op(B) (K x N).  TA: A stored K x M (lda over m);
 // TB: B stored N x K (ldb over k).  64x64 tile per block of 4 waves, each wave
 // a 32x32 sub-tile of 2x2 MFMA 16x16x32 blocks; operands staged through LDS
-// with K contiguous so each lane's fragment is one 16-byte read.
+// with K contiguous so each lane's fragment is one 16-byte read.  Tiles wholly
+// in bounds, with 16-byte aligned operand rows, are fetched with one 16-byte
+// global load per thread and operand; edge tiles element by element.
 template <int EPI, bool TA, bool TB>
 __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
     __shared__ __align__(16) bf16 As[kTM][kLdsK];
@@ -60,13 +65,37 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kb = g.kslice > 0 ? (int)blockIdx.z * g.kslice : 0;
+    const int ke = g.kslice > 0 ? min(g.K, kb + g.kslice) : g.K;
+    const bool vec_ok = (g.lda % 8) == 0 && (g.ldb % 8) == 0 && (((uintptr_t)g.A | (uintptr_t)g.B) & 15) == 0 &&
+                        m0 + kTM <= g.M && n0 + kTN <= g.N;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16 zero = (bf16)0.0f;
-    for (int k0 = 0; k0 < g.K; k0 += kTK) {
+    for (int k0 = kb; k0 < ke; k0 += kTK) {
+        if (vec_ok && k0 + kTK <= ke) {
+            if (!TA) {
+                const int r = t >> 2, kc = (t & 3) * 8;
+                *(bf16x8*)&As[r][kc] = *(const bf16x8*)&g.A[(int64_t)(m0 + r) * g.lda + k0 + kc];
+            } else {
+                const int kk = t >> 3, mc = (t & 7) * 8;
+                const bf16x8 v = *(const bf16x8*)&g.A[(int64_t)(k0 + kk) * g.lda + m0 + mc];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) As[mc + i][kk] = v[i];
+            }
+            if (!TB) {
+                const int kk = t >> 3, nc = (t & 7) * 8;
+                const bf16x8 v = *(const bf16x8*)&g.B[(int64_t)(k0 + kk) * g.ldb + n0 + nc];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) Bs[nc + i][kk] = v[i];
+            } else {
+                const int r = t >> 2, kc = (t & 3) * 8;
+                *(bf16x8*)&Bs[r][kc] = *(const bf16x8*)&g.B[(int64_t)(n0 + r) * g.ldb + k0 + kc];
+            }
+        } else {
         // ---- stage A tile (64 x 32) as As[m][k]
         if (!TA) {
             const int r = t >> 2, kc = (t & 3) * 8;
@@ -74,7 +103,7 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int gk = k0 + kc + i;
-                As[r][kc + i] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.lda + gk] : zero;
+                As[r][kc + i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : zero;
             }
         } else {
             const int kk = t >> 3, mc = (t & 7) * 8;
@@ -82,7 +111,7 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int gm = m0 + mc + i;
-                As[mc + i][kk] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gk * g.lda + gm] : zero;
+                As[mc + i][kk] = (gm < g.M && gk < ke) ? g.A[(int64_t)gk * g.lda + gm] : zero;
             }
         }
         // ---- stage B tile (32 x 64) as Bs[n][k]
@@ -92,7 +121,7 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int gn = n0 + nc + i;
-                Bs[nc + i][kk] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.ldb + gn] : zero;
+                Bs[nc + i][kk] = (gn < g.N && gk < ke) ? g.B[(int64_t)gk * g.ldb + gn] : zero;
             }
         } else {
             const int r = t >> 2, kc = (t & 3) * 8;
@@ -100,8 +129,9 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int gk = k0 + kc + i;
-                Bs[r][kc + i] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gn * g.ldb + gk] : zero;
+                Bs[r][kc + i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : zero;
             }
+        }
         }
         __syncthreads();
         bf16x8 a[2], b[2];
@@ -127,7 +157,9 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
                 if (row >= g.M || col >= g.N) continue;
                 const int64_t o = (int64_t)row * g.ldc + col;
                 const float v = acc[i][j][r];
-                if (EPI == EPI_STORE) {
+                if (EPI == EPI_STORE && g.kslice > 0) {
+                    g.part[(int64_t)blockIdx.z * g.M * g.ldc + o] = v;
+                } else if (EPI == EPI_STORE) {
                     g.C[o] = v;
                 } else if (EPI == EPI_BIAS) {
                     g.C[o] = v + g.bias[col];
@@ -139,6 +171,18 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
                     g.H[o] = (bf16)(v * dsilu_f(g.Zin[o]));
                 }
             }
+}
+
+// C = the S split-K partial products summed in slice order (deterministic).
+__global__ void __launch_bounds__(256) splitk_sum(int M, int N, int ldc, int S, const float* __restrict__ part,
+                                                  float* __restrict__ C) {
+    const int64_t total = (int64_t)M * N, plane = (int64_t)M * ldc;
+    for (int64_t x = blockIdx.x * 256LL + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
+        const int64_t o = (x / N) * ldc + x % N;
+        float s = 0.0f;
+        for (int z = 0; z < S; ++z) s += part[z * plane + o];
+        C[o] = s;
+    }
 }
 
 // dY = 2 (Y - T) / (B N) as BF16; per-block partial sums of (Y - T)^2.
@@ -400,8 +444,22 @@ struct slaq_closure_s {
 namespace slaq {
 
 struct ClosureWs {
-    size_t x, z[3], h[3], y, dy, dyf, dh, dz, part, total;
+    size_t x, z[3], h[3], y, dy, dyf, dh, dz, part, kpart, total;
 };
+
+constexpr int kSplitKMin = 64;                // fewest rows of K per slice
+constexpr size_t kSplitKBytes = 16u << 20;    // largest partial-product buffer
+
+// slices of K for a weight-gradient product (M x N, K = batch rows): enough
+// workgroups to fill the chip while each slice keeps at least kSplitKMin rows
+// and the partials fit kSplitKBytes; 1 means no split
+static int splitk_slices(int M, int N, int64_t K) {
+    const int64_t tiles = (int64_t)((N + kTN - 1) / kTN) * ((M + kTM - 1) / kTM);
+    int64_t s = K / kSplitKMin;
+    s = std::min<int64_t>(s, std::max<int64_t>(1, 256 / tiles));
+    s = std::min<int64_t>(s, (int64_t)(kSplitKBytes / ((size_t)M * N * 4)));
+    return (int)std::max<int64_t>(1, s);
+}
 
 static ClosureWs closure_ws(const slaq_closure_s* c, int64_t B) {
     ClosureWs L{};
@@ -422,6 +480,12 @@ static ClosureWs closure_ws(const slaq_closure_s* c, int64_t B) {
     L.dh = take((size_t)B * H * 4);
     L.dz = take((size_t)B * H * 2);
     L.part = take(1024 * 8);
+    size_t kp = 0;
+    for (int l = 0; l < 4; ++l) {
+        const int S = splitk_slices(c->dims[l], c->dims[l + 1], B);
+        if (S > 1) kp = std::max(kp, (size_t)S * c->dims[l] * c->dims[l + 1] * 4);
+    }
+    L.kpart = take(kp);
     L.total = off;
     return L;
 }
@@ -430,6 +494,25 @@ template <int EPI, bool TA, bool TB>
 static slaq_status gemm(const GemmArgs& a, hipStream_t st, const char* tag) {
     dim3 grid((a.N + kTN - 1) / kTN, (a.M + kTM - 1) / kTM);
     SLAQ_TIMED(tag, st, hipLaunchKernelGGL((mlp_gemm<EPI, TA, TB>), grid, dim3(256), 0, st, a));
+    SLAQ_LAUNCHED();
+    return SLAQ_OK;
+}
+
+// C = A^T B with A stored K x M: split over K when that fills more of the chip
+// (partials into the workspace, then a fixed-order sum)
+static slaq_status gemm_wgrad(GemmArgs a, float* kpart, hipStream_t st, const char* tag) {
+    const int S = splitk_slices(a.M, a.N, a.K);
+    if (S <= 1) return gemm<EPI_STORE, true, false>(a, st, tag);
+    const int per = (a.K + S - 1) / S;
+    a.kslice = (per + kTK - 1) / kTK * kTK;
+    const int Z = (a.K + a.kslice - 1) / a.kslice;
+    a.part = kpart;
+    dim3 grid((a.N + kTN - 1) / kTN, (a.M + kTM - 1) / kTM, Z);
+    SLAQ_TIMED(tag, st, hipLaunchKernelGGL((mlp_gemm<EPI_STORE, true, false>), grid, dim3(256), 0, st, a));
+    SLAQ_LAUNCHED();
+    const int64_t total = (int64_t)a.M * a.N;
+    const int nb = (int)std::min<int64_t>(1024, (total + 255) / 256);
+    hipLaunchKernelGGL(splitk_sum, dim3(nb), dim3(256), 0, st, a.M, a.N, a.ldc, Z, (const float*)kpart, a.C);
     SLAQ_LAUNCHED();
     return SLAQ_OK;
 }
@@ -503,7 +586,7 @@ static slaq_status closure_bwd(slaq_closure_s* c, const bf16* X, const float* Yt
         gw.ldb = dout;
         gw.C = c->grad + c->off[2 * l];
         gw.ldc = dout;
-        SLAQ_TRY((gemm<EPI_STORE, true, false>(gw, st, "mlp_bwd")));
+        SLAQ_TRY(gemm_wgrad(gw, (float*)(ws + L.kpart), st, "mlp_bwd"));
         // db_l = column sums of dcur (FP32 for the output layer)
         if (l == 3)
             hipLaunchKernelGGL(col_sum<float>, dim3((dout + 63) / 64), dim3(256), 0, st, (int)B, dout, dyf,
