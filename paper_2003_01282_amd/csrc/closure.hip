@@ -25,7 +25,10 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 namespace slaq {
 
-constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsK = 40;  // tile sizes; LDS row stride (bf16) avoids bank conflicts
+// tile sizes: 64 x 64 outputs per block, K staged 128 deep (four MFMA K-steps
+// of 32); LDS row stride 136 bf16 = 68 dwords puts the 16 rows a fragment read
+// touches on distinct 4-bank groups
+constexpr int kTM = 64, kTN = 64, kTK = 128, kLdsK = kTK + 8;
 constexpr int kDinPad = 32;
 
 enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_DSILU = 3 };
@@ -55,11 +58,69 @@ __device__ __forceinline__ float dsilu_f(float z) {
 // C (M x N) = op(A) (M x K) * op(B) (K x N).  TA: A stored K x M (lda over m);
 // TB: B stored N x K (ldb over k).  64x64 tile per block of 4 waves, each wave
 // a 32x32 sub-tile of 2x2 MFMA 16x16x32 blocks; operands staged through LDS
-// with K contiguous so each lane's fragment is one 16-byte read.  Tiles wholly
-// in bounds, with 16-byte aligned operand rows, are fetched with one 16-byte
-// global load per thread and operand; edge tiles element by element.
+// with K contiguous so each lane's fragment is one 16-byte read.  A stage of
+// kTK rows of K is fetched with all of a thread's loads in flight at once: one
+// 16-byte load per 8 elements when the tile is wholly in bounds and the operand
+// rows are 16-byte aligned, element by element (zero outside) otherwise.
+template <bool TRANS>
+__device__ __forceinline__ void stage_operand(bf16 (*S)[kLdsK], const bf16* __restrict__ X, int ld, int o0, int olim,
+                                              int k0, int klim, bool vec, int t) {
+    // TRANS: X stored K x (outer), rows of K at stride ld; else (outer) x K
+    constexpr int kVec = kTM * kTK / 8 / 256;  // 16-byte vectors per thread
+    if (vec) {
+        bf16x8 v[kVec];
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) {
+            const int q = t + 256 * j;
+            if (TRANS) {
+                const int kk = q / (kTM / 8), oc = (q % (kTM / 8)) * 8;
+                v[j] = *(const bf16x8*)&X[(int64_t)(k0 + kk) * ld + o0 + oc];
+            } else {
+                const int r = q / (kTK / 8), kc = (q % (kTK / 8)) * 8;
+                v[j] = *(const bf16x8*)&X[(int64_t)(o0 + r) * ld + k0 + kc];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) {
+            const int q = t + 256 * j;
+            if (TRANS) {
+                const int kk = q / (kTM / 8), oc = (q % (kTM / 8)) * 8;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) S[oc + i][kk] = v[j][i];
+            } else {
+                const int r = q / (kTK / 8), kc = (q % (kTK / 8)) * 8;
+                *(bf16x8*)&S[r][kc] = v[j];
+            }
+        }
+        return;
+    }
+    const bf16 zero = (bf16)0.0f;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) {
+        const int q = t + 256 * j;
+        if (TRANS) {
+            const int kk = q / (kTM / 8), oc = (q % (kTM / 8)) * 8;
+            const int gk = k0 + kk;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int go = o0 + oc + i;
+                S[oc + i][kk] = (go < olim && gk < klim) ? X[(int64_t)gk * ld + go] : zero;
+            }
+        } else {
+            const int r = q / (kTK / 8), kc = (q % (kTK / 8)) * 8;
+            const int go = o0 + r;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int gk = k0 + kc + i;
+                S[r][kc + i] = (go < olim && gk < klim) ? X[(int64_t)go * ld + gk] : zero;
+            }
+        }
+    }
+}
+
 template <int EPI, bool TA, bool TB>
 __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
+    static_assert(kTM == kTN, "one staging routine serves both operands");
     __shared__ __align__(16) bf16 As[kTM][kLdsK];
     __shared__ __align__(16) bf16 Bs[kTN][kLdsK];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -74,75 +135,26 @@ __global__ void __launch_bounds__(256) mlp_gemm(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16 zero = (bf16)0.0f;
     for (int k0 = kb; k0 < ke; k0 += kTK) {
-        if (vec_ok && k0 + kTK <= ke) {
-            if (!TA) {
-                const int r = t >> 2, kc = (t & 3) * 8;
-                *(bf16x8*)&As[r][kc] = *(const bf16x8*)&g.A[(int64_t)(m0 + r) * g.lda + k0 + kc];
-            } else {
-                const int kk = t >> 3, mc = (t & 7) * 8;
-                const bf16x8 v = *(const bf16x8*)&g.A[(int64_t)(k0 + kk) * g.lda + m0 + mc];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) As[mc + i][kk] = v[i];
-            }
-            if (!TB) {
-                const int kk = t >> 3, nc = (t & 7) * 8;
-                const bf16x8 v = *(const bf16x8*)&g.B[(int64_t)(k0 + kk) * g.ldb + n0 + nc];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) Bs[nc + i][kk] = v[i];
-            } else {
-                const int r = t >> 2, kc = (t & 3) * 8;
-                *(bf16x8*)&Bs[r][kc] = *(const bf16x8*)&g.B[(int64_t)(n0 + r) * g.ldb + k0 + kc];
-            }
-        } else {
-        // ---- stage A tile (64 x 32) as As[m][k]
-        if (!TA) {
-            const int r = t >> 2, kc = (t & 3) * 8;
-            const int gm = m0 + r;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gk = k0 + kc + i;
-                As[r][kc + i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : zero;
-            }
-        } else {
-            const int kk = t >> 3, mc = (t & 7) * 8;
-            const int gk = k0 + kk;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gm = m0 + mc + i;
-                As[mc + i][kk] = (gm < g.M && gk < ke) ? g.A[(int64_t)gk * g.lda + gm] : zero;
-            }
-        }
-        // ---- stage B tile (32 x 64) as Bs[n][k]
-        if (!TB) {
-            const int kk = t >> 3, nc = (t & 7) * 8;
-            const int gk = k0 + kk;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gn = n0 + nc + i;
-                Bs[nc + i][kk] = (gn < g.N && gk < ke) ? g.B[(int64_t)gk * g.ldb + gn] : zero;
-            }
-        } else {
-            const int r = t >> 2, kc = (t & 3) * 8;
-            const int gn = n0 + r;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gk = k0 + kc + i;
-                Bs[r][kc + i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : zero;
-            }
-        }
-        }
+        const bool vec = vec_ok && k0 + kTK <= ke;
+        stage_operand<TA>(As, g.A, g.lda, m0, g.M, k0, ke, vec, t);
+        stage_operand<!TB>(Bs, g.B, g.ldb, n0, g.N, k0, ke, vec, t);
         __syncthreads();
-        bf16x8 a[2], b[2];
+        const int kn = min(kTK, ke - k0);
+        for (int kk = 0; kk < kn; kk += 32) {
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8];
+            for (int i = 0; i < 2; ++i)
+                a[i] = *(const bf16x8*)&As[wm + i * 16 + (lane & 15)][kk + (lane >> 4) * 8];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8];
+            for (int j = 0; j < 2; ++j)
+                b[j] = *(const bf16x8*)&Bs[wn + j * 16 + (lane & 15)][kk + (lane >> 4) * 8];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
     // ---- epilogue: lane holds rows (lane/16)*4 + r of column lane%16
@@ -220,17 +232,33 @@ __global__ void __launch_bounds__(256) loss_final(const double* __restrict__ par
     if (threadIdx.x == 0) loss[0] = (float)(red[0] * inv_count);
 }
 
-// db[n] = sum over rows of D[row][n] (BF16 or FP32 input), fixed order.
+// db[n] = sum over rows of D[row][n] (BF16 or FP32 input), fixed order: 16
+// row groups per column, each summing every 16th row into four interleaved
+// accumulators, then the groups in order.
 template <typename T>
-__global__ void __launch_bounds__(256) col_sum(int rows, int N, const T* __restrict__ D, float* __restrict__ db) {
-    const int c = blockIdx.x * 64 + (threadIdx.x & 63), r0 = threadIdx.x >> 6;
-    float s = 0.0f;
-    if (c < N)
-        for (int r = r0; r < rows; r += 4) s += (float)D[(int64_t)r * N + c];
-    __shared__ float red[4][64];
-    red[r0][threadIdx.x & 63] = s;
+__global__ void __launch_bounds__(1024) col_sum(int rows, int N, const T* __restrict__ D, float* __restrict__ db) {
+    const int lane = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    if (c < N) {
+        int r = r0;
+        for (; r + 48 < rows; r += 64) {
+            s0 += (float)D[(int64_t)r * N + c];
+            s1 += (float)D[(int64_t)(r + 16) * N + c];
+            s2 += (float)D[(int64_t)(r + 32) * N + c];
+            s3 += (float)D[(int64_t)(r + 48) * N + c];
+        }
+        for (; r < rows; r += 16) s0 += (float)D[(int64_t)r * N + c];
+    }
+    __shared__ float red[16][64];
+    red[r0][lane] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    if (threadIdx.x < 64 && c < N) db[c] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    if (threadIdx.x < 64 && c < N) {
+        float t = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) t += red[g][lane];
+        db[c] = t;
+    }
 }
 
 __global__ void __launch_bounds__(256) adam_step(int64_t P, float* __restrict__ w, bf16* __restrict__ wb,
@@ -447,7 +475,7 @@ struct ClosureWs {
     size_t x, z[3], h[3], y, dy, dyf, dh, dz, part, kpart, total;
 };
 
-constexpr int kSplitKMin = 64;                // fewest rows of K per slice
+constexpr int kSplitKMin = kTK;               // fewest rows of K per slice
 constexpr size_t kSplitKBytes = 16u << 20;    // largest partial-product buffer
 
 // slices of K for a weight-gradient product (M x N, K = batch rows): enough
@@ -589,10 +617,10 @@ static slaq_status closure_bwd(slaq_closure_s* c, const bf16* X, const float* Yt
         SLAQ_TRY(gemm_wgrad(gw, (float*)(ws + L.kpart), st, "mlp_bwd"));
         // db_l = column sums of dcur (FP32 for the output layer)
         if (l == 3)
-            hipLaunchKernelGGL(col_sum<float>, dim3((dout + 63) / 64), dim3(256), 0, st, (int)B, dout, dyf,
+            hipLaunchKernelGGL(col_sum<float>, dim3((dout + 63) / 64), dim3(1024), 0, st, (int)B, dout, dyf,
                                c->grad + c->off[2 * l + 1]);
         else
-            hipLaunchKernelGGL(col_sum<bf16>, dim3((dout + 63) / 64), dim3(256), 0, st, (int)B, dout, dcur,
+            hipLaunchKernelGGL(col_sum<bf16>, dim3((dout + 63) / 64), dim3(1024), 0, st, (int)B, dout, dcur,
                                c->grad + c->off[2 * l + 1]);
         SLAQ_LAUNCHED();
         if (l == 0) break;
