@@ -84,7 +84,9 @@ def measured_traffic(args):
 
 
 def cpu_baseline(csr, nv, m, seed, budget_s=25.0):
-    """The FP64 oracle's Lanczos loop on a probe subset of the same graph."""
+    """The FP64 oracle's Lanczos loop on a probe subset of the same graph.
+    Returns the timing record and the oracle's (alpha, beta, steps) of those
+    probes, which the caller compares with the GPU's."""
     from oracle import slq as O
     g = O.build_graph(csr.n, csr.row_ptr, csr.col_idx)
     V = O.rademacher(csr.n, nv, seed)
@@ -94,14 +96,14 @@ def cpu_baseline(csr, nv, m, seed, budget_s=25.0):
     one = max(time.perf_counter() - t0, 1e-6)
     probes = int(max(1, min(nv, budget_s / (one * m))))
     t0 = time.perf_counter()
-    O.lanczos(g, probes, m, seed, probes=V[:, :probes])
+    ref = O.lanczos(g, probes, m, seed, probes=V[:, :probes])
     dt = time.perf_counter() - t0
     try:
         from threadpoolctl import threadpool_info
         blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         blas_threads = 1
-    return {
+    return ref, {
         "value": csr.nnz * probes * m / dt,
         "unit": "nnz*probes*steps/s",
         "cores": 1,
@@ -541,10 +543,22 @@ def main():
 
     # the oracle needs a host copy of the graph: timed for host-generated
     # workloads only (a scale-26 graph takes ~25 GB as a scipy matrix)
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu_baseline and csr is not None:
         log("cpu baseline (oracle on a probe subset)")
-        cpu = cpu_baseline(csr, nv, m, args.seed)
+        ref, cpu = cpu_baseline(csr, nv, m, args.seed)
+        # full-size parity on the oracle's probes: the GPU's coefficients of the
+        # last timed step against the oracle's FP64 ones
+        k = ref[0].shape[0]
+        ga, gb, gs = alpha[:k].cpu().numpy(), beta[:k].cpu().numpy(), steps[:k].cpu().numpy()
+
+        def rel(x, y):
+            return float(np.max(np.abs(x - y) / np.maximum(np.abs(y), 1e-6)))
+
+        parity = {"probes": k, "max_rel_alpha": rel(ga, ref[0]), "max_rel_beta": rel(gb, ref[1]),
+                  "steps_equal": bool(np.array_equal(gs, ref[2])), "tol": 1e-4}
+        parity["ok"] = parity["steps_equal"] and max(parity["max_rel_alpha"], parity["max_rel_beta"]) <= 1e-4
+        log(f"parity vs oracle: {parity}")
         cpu["cores"] = 1
         try:
             cpu["cpu_model"] = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
@@ -584,6 +598,7 @@ def main():
                          "nnz_probes_steps_per_s": nnz * nv * m / (loop_ms * 1e-3) if loop_ms else None},
         "stages": stages,
         "heat_sane": sanity,
+        "parity": parity,
         "variance_reduction": vr,
         "cpu_baseline": cpu,
     }

@@ -26,11 +26,13 @@ def oracle_layers(net):
     return [(bf16_round(W.cpu().numpy()), b.cpu().numpy().astype(np.float64)) for W, b in net.layers()]
 
 
-def test_forward_and_gradients_against_fp64_reference():
-    print("\n[gpu] closure gradient check", flush=True)
+# B = 300: ragged against the 64-row tiles, the weight gradients' last K slice
+# partial; B = 1024: every hidden-layer tile and K slice whole (16-byte loads)
+@pytest.mark.parametrize("B", [300, 1024])
+def test_forward_and_gradients_against_fp64_reference(B):
+    print(f"\n[gpu] closure gradient check, batch {B}", flush=True)
     net = S.Closure(d_in=10, hidden=256, nt=256, seed=7)
     rng = np.random.default_rng(0)
-    B = 300  # ragged against the 64-row tiles
     X = np.zeros((B, 32), dtype=np.float32)
     X[:, :5] = np.sort(rng.uniform(0, 2, (B, 5)), axis=1)
     X[:, 5:10] = rng.dirichlet(np.ones(5), B)
