@@ -64,8 +64,8 @@ __host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int B) {
     const int F = (nv + 3) / 4;
     BatchLds L{};
     size_t off = 0;
-    L.r = off;
-    off += (size_t)n_max * F * 16;
+    L.r = off;  // n_max rows and one zero row after the graph's last
+    off += (size_t)(n_max + 1) * F * 16;
     L.dinv = off;
     off += ((size_t)n_max * 4 + 15) / 16 * 16;
     L.st = off;  // per probe: sigma, tau, a, active, steps (doubles)
@@ -200,6 +200,8 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -one : one) : 0.0f;
             R[x] = make_float4(v[0], v[1], v[2], v[3]);
         }
+        // row n stays zero: column ids outside the graph are clamped to it
+        for (int x = t; x < F; x += B) R[n * ldq + x] = make_float4(0.f, 0.f, 0.f, 0.f);
         init_probe_state(t, B, a.nv, F, a.m, 1.0 / sqrt((double)n), pst, coef);
         // every (probe, step) entry of alpha and beta is written below (0 once
         // a probe has stopped)
@@ -234,15 +236,13 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 // kBatchUnroll column ids, then their LDS reads, are in flight at
                 // once; the products are added in nonzero order as below
                 for (; kk + kBatchUnroll <= e; kk += kBatchUnroll) {
-                    int c[kBatchUnroll];
+                    // a column outside the graph reads the zero row n: ignored
+                    unsigned c[kBatchUnroll];
 #pragma unroll
-                    for (int u = 0; u < kBatchUnroll; ++u) c[u] = (int)(col[kk + u] - base);
+                    for (int u = 0; u < kBatchUnroll; ++u) c[u] = min((unsigned)(int)(col[kk + u] - base), (unsigned)n);
                     float4 x[kBatchUnroll];
 #pragma unroll
-                    for (int u = 0; u < kBatchUnroll; ++u) {
-                        const bool in = (unsigned)c[u] < (unsigned)n;  // column outside the graph: ignored
-                        x[u] = in ? R[c[u] * ldq + q] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
+                    for (int u = 0; u < kBatchUnroll; ++u) x[u] = R[c[u] * ldq + q];
 #pragma unroll
                     for (int u = 0; u < kBatchUnroll; ++u) {
                         acc.x += x[u].x;
@@ -252,8 +252,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                     }
                 }
                 for (; kk < e; ++kk) {
-                    const int c = (int)(col[kk] - base);
-                    if ((unsigned)c >= (unsigned)n) continue;  // column outside the graph: ignored
+                    const unsigned c = min((unsigned)(int)(col[kk] - base), (unsigned)n);
                     const float4 x = R[c * ldq + q];
                     acc.x += x.x;
                     acc.y += x.y;
