@@ -252,8 +252,8 @@ slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, i
  * nodes in the whole batch.  Graphs whose probe block (n ceil(nv/4) 16 bytes)
  * fits in 64 KB are bucketed by node count and keep it in LDS; all larger
  * graphs form one more bucket that runs the same per-graph Lanczos with the
- * probe blocks in a global workspace: one slot of 3 n_max ceil(nv/4) 16 +
- * 4 n_max bytes per workgroup its launch keeps resident, at most 16 GB
+ * probe blocks in a global workspace: one slot of 3 (n_max + 1) ceil(nv/4)
+ * 16 + 4 n_max bytes per workgroup its launch keeps resident, at most 16 GB
  * (slaq_batch_workspace; the caller's via slaq_batch_set_workspace, else
  * allocated by the first run and freed by slaq_batch_destroy).
  *

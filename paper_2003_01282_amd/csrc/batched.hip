@@ -323,8 +323,8 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
 
 // Graphs whose probe block does not fit in LDS: the same per-graph Lanczos
 // with X_j, X_{j-1}, w and D^-1/2 in the workgroup's slot of a global
-// workspace (slot = blockIdx.x, slot_quads quads per block, slot_n floats of
-// D^-1/2).  Rows are taken in passes of bact / F; nothing is held per row in
+// workspace (slot = blockIdx.x: three buffers of slot_quads quads, the
+// largest graph's rows plus one zero row, and slot_n floats of D^-1/2).  Rows are taken in passes of bact / F; nothing is held per row in
 // registers, so the kernel serves any graph size.  X_{j+1} overwrites
 // X_{j-1}, and the two buffers swap roles after every step.
 template <int B>
@@ -381,6 +381,12 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
                 v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -one : one) : 0.0f;
             X[x] = make_float4(v[0], v[1], v[2], v[3]);
         }
+        // row n of both rotating buffers stays zero: column ids outside the
+        // graph are clamped to it
+        for (int x = t; x < F; x += B) {
+            X[(int64_t)n * F + x] = make_float4(0.f, 0.f, 0.f, 0.f);
+            P[(int64_t)n * F + x] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         init_probe_state(t, B, a.nv, F, a.m, 1.0 / sqrt((double)n), pst, coef);
         double* const gal = a.alpha + (int64_t)g * a.nv * a.m;
         double* const gbe = a.beta + (int64_t)g * a.nv * a.m;
@@ -402,15 +408,13 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
                 float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                 int64_t kk = s;
                 for (; kk + kBatchUnroll <= e; kk += kBatchUnroll) {
-                    int c[kBatchUnroll];
+                    // a column outside the graph reads the zero row n: ignored
+                    unsigned c[kBatchUnroll];
 #pragma unroll
-                    for (int u = 0; u < kBatchUnroll; ++u) c[u] = (int)(col[kk + u] - base);
+                    for (int u = 0; u < kBatchUnroll; ++u) c[u] = min((unsigned)(int)(col[kk + u] - base), (unsigned)n);
                     float4 x[kBatchUnroll];
 #pragma unroll
-                    for (int u = 0; u < kBatchUnroll; ++u) {
-                        const bool in = (unsigned)c[u] < (unsigned)n;  // column outside the graph: ignored
-                        x[u] = in ? X[(int64_t)c[u] * F + q] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
+                    for (int u = 0; u < kBatchUnroll; ++u) x[u] = X[(int64_t)c[u] * F + q];
 #pragma unroll
                     for (int u = 0; u < kBatchUnroll; ++u) {
                         acc.x += x[u].x;
@@ -420,8 +424,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
                     }
                 }
                 for (; kk < e; ++kk) {
-                    const int c = (int)(col[kk] - base);
-                    if ((unsigned)c >= (unsigned)n) continue;
+                    const unsigned c = min((unsigned)(int)(col[kk] - base), (unsigned)n);
                     const float4 x = X[(int64_t)c * F + q];
                     acc.x += x.x;
                     acc.y += x.y;
@@ -763,7 +766,7 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         c.n_hi = (int)top;
         const int Fq = (nv + 3) / 4;
         c.global = c.n_hi > lds_cap_n;
-        const size_t slot_bytes = (size_t)3 * c.n_hi * Fq * 16 + (size_t)c.n_hi * 4;
+        const size_t slot_bytes = (size_t)3 * (c.n_hi + 1) * Fq * 16 + (size_t)c.n_hi * 4;
         if (c.global)
             c.slots = (int)std::max<size_t>(1, std::min<size_t>(kGlobalWsBudget / slot_bytes,
                                                                 (size_t)device_cus() * 8));
@@ -783,7 +786,7 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
             // one slot per workgroup the chosen block keeps resident (the
             // autotuner's other sizes are capped to as many)
             c.slots = std::min(c.slots, c.grid);
-            b->ws_quads = (int64_t)c.slots * 3 * c.n_hi * Fq;
+            b->ws_quads = (int64_t)c.slots * 3 * (c.n_hi + 1) * Fq;  // + a zero row per buffer
             b->ws_floats = (int64_t)c.slots * c.n_hi;
             b->ws_bytes = align_up((size_t)b->ws_quads * 16, 256) + align_up((size_t)b->ws_floats * 4, 256);
         }
@@ -897,7 +900,7 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
             float* gwsd = (float*)((char*)b->ws + align_up((size_t)b->ws_quads * 16, 256));
             SLAQ_TIMED("batch_slq", bs,
                        hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, bs, a, gws,
-                                          (int64_t)c.n_hi * Fq, gwsd, (int64_t)c.n_hi));
+                                          (int64_t)(c.n_hi + 1) * Fq, gwsd, (int64_t)c.n_hi));
         } else {
             BatchKernel kern = pick_kernel(c.block, c.ipt);
             SLAQ_TIMED("batch_slq", bs, hipLaunchKernelGGL(kern, dim3(grid), dim3(c.block), c.lds, bs, a));
