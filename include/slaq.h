@@ -330,7 +330,13 @@ slaq_status slaq_batch_destroy(slaq_batch_t b);
  * create: Glorot-uniform init from SplitMix64(seed); info: parameter count,
  * offsets of W1 b1 W2 b2 W3 b3 W4 b4 in the FP32 parameter vector
  * (W row-major d_in x d_out), layer widths.  get (which 0 = weights, 1 =
- * gradients of the last train_step) / set copy that vector device-to-device.
+ * gradients of the last train_step, 2 / 3 = Adam first / second moments) /
+ * set copy such a vector device-to-device (set: the weights, optionally
+ * zeroing the optimizer state).  get_step: the number of Adam steps taken
+ * (host int, no device work).  set_optimizer: restores the Adam moments and
+ * the step count, so that a handle given a checkpoint's weights (set with
+ * reset_optimizer = 0) and optimizer state continues training exactly as the
+ * handle it was taken from.
  * train_step: x BF16 [batch][32], y FP32 [batch][nt]; writes the gradients,
  * the loss (device float, optional) and, when lr > 0, one Adam step.
  * forward: y_hat FP32 [batch][nt].
@@ -353,6 +359,8 @@ slaq_status slaq_closure_info(slaq_closure_t c, int64_t* n_params, int64_t* offs
 slaq_status slaq_closure_workspace(slaq_closure_t c, int64_t batch, size_t* bytes);
 slaq_status slaq_closure_get(slaq_closure_t c, int which, float* dst, void* stream);
 slaq_status slaq_closure_set(slaq_closure_t c, const float* src, int reset_optimizer, void* stream);
+slaq_status slaq_closure_get_step(slaq_closure_t c, int* step);
+slaq_status slaq_closure_set_optimizer(slaq_closure_t c, const float* m1, const float* m2, int step, void* stream);
 slaq_status slaq_closure_forward(slaq_closure_t c, const void* x, int64_t batch, float* yhat, void* workspace,
                                  size_t ws_bytes, void* stream);
 slaq_status slaq_closure_train_step(slaq_closure_t c, const void* x, const float* y, int64_t batch, float lr,

@@ -9,6 +9,9 @@ label.  Inference needs only the mf-step run: y_hat = MLP(features), per-probe
 Q_hat = Q_mf exp(y_hat) clamped to the bracket, heat = n/nv sum_p Q_hat; graphs
 whose raw prediction left the bracket are flagged and recomputed by plain SLQ.
 """
+import json
+import os
+import struct
 from dataclasses import dataclass
 
 import numpy as np
@@ -148,14 +151,22 @@ def heat_from_q(q, graph_n, nv):
     return q.view(G, nv, -1).sum(dim=1) * (graph_n.to(torch.float64) / nv)[:, None]
 
 
-def train(net, data, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
-    """Minibatch Adam on the kernels' train step; returns the loss history."""
+def epoch_seed(seed, epoch):
+    """Seed of one epoch's sample order: a function of (seed, epoch) only, so a
+    run resumed at an epoch boundary draws the orders of the uninterrupted one."""
+    return int(np.random.SeedSequence([int(seed), int(epoch)]).generate_state(1, dtype=np.uint64)[0] >> 1)
+
+
+def train(net, data, epochs=20, batch=1024, lr=1e-3, seed=0, log=None, first_epoch=0, checkpoint=None):
+    """Minibatch Adam on the kernels' train step, epochs first_epoch ..
+    first_epoch + epochs - 1; with `checkpoint` (a path) the network and
+    optimizer state are saved after every epoch.  Returns the loss history."""
     P = data.x.shape[0]
     gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     hist = []
-    for ep in range(epochs):
+    for ep in range(first_epoch, first_epoch + epochs):
+        gen.manual_seed(epoch_seed(seed, ep))
         perm = torch.randperm(P, device="cuda", generator=gen)
         tot, nb = 0.0, 0
         for s in range(0, P, batch):
@@ -166,7 +177,58 @@ def train(net, data, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
         hist.append(tot / max(nb, 1))
         if log:
             log(f"epoch {ep} loss {hist[-1]:.3e}")
+        if checkpoint is not None:
+            save_checkpoint(net, checkpoint, epoch=ep + 1, seed=seed)
     return hist
+
+
+CHECKPOINT_FORMAT = "slaq-closure-checkpoint-1"
+_CKPT_ARRAYS = (("weights", 0), ("adam_m1", 2), ("adam_m2", 3))
+
+
+def save_checkpoint(net, path, epoch=0, seed=0):
+    """Network and optimizer state as one file: an 8-byte little-endian
+    header length, a JSON header (shape, Adam step count, epochs completed,
+    shuffling seed, array names), then the FP32 weights and the two Adam
+    moment vectors, little-endian, n_params values each."""
+    header = {"format": CHECKPOINT_FORMAT, "d_in": net.d_in, "hidden": net.hidden, "nt": net.nt,
+              "n_params": net.n_params, "offsets": net.offsets, "dims": net.dims, "adam_step": net.step(),
+              "epoch": int(epoch), "seed": int(seed), "arrays": [a for a, _ in _CKPT_ARRAYS], "dtype": "<f4"}
+    head = json.dumps(header).encode()
+    tmp = f"{path}.tmp"
+    with open(tmp, "wb") as f:
+        f.write(struct.pack("<Q", len(head)))
+        f.write(head)
+        for _, which in _CKPT_ARRAYS:
+            f.write(net.get(which).cpu().numpy().astype("<f4").tobytes())
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path):
+    """A new network with the checkpoint's weights and optimizer state, and
+    the header (its "epoch" is the first_epoch to resume training at)."""
+    with open(path, "rb") as f:
+        (hl,) = struct.unpack("<Q", f.read(8))
+        header = json.loads(f.read(hl).decode())
+        if header.get("format") != CHECKPOINT_FORMAT:
+            raise ValueError(f"{path}: not a closure checkpoint ({header.get('format')!r})")
+        P = int(header["n_params"])
+        vecs = {}
+        for name in header["arrays"]:
+            buf = f.read(4 * P)
+            if len(buf) != 4 * P:
+                raise ValueError(f"{path}: truncated at {name}")
+            vecs[name] = np.frombuffer(buf, dtype="<f4").astype(np.float32)
+        if f.read(1):
+            raise ValueError(f"{path}: trailing bytes")
+    # the file is whole: only now is the device touched
+    vecs = {k: torch.from_numpy(v).cuda() for k, v in vecs.items()}
+    net = S.Closure(d_in=header["d_in"], hidden=header["hidden"], nt=header["nt"])
+    if net.n_params != P or net.offsets != header["offsets"] or net.dims != header["dims"]:
+        raise ValueError(f"{path}: parameter layout does not match this library")
+    net.set(vecs["weights"], reset_optimizer=False)
+    net.set_optimizer(vecs["adam_m1"], vecs["adam_m2"], header["adam_step"])
+    return net, header
 
 
 def infer(net, data, tol=1e-3):

@@ -729,8 +729,26 @@ slaq_status slaq_closure_workspace(slaq_closure_t c, int64_t batch, size_t* byte
 // which: 0 = FP32 master weights, 1 = gradients of the last backward pass
 slaq_status slaq_closure_get(slaq_closure_t c, int which, float* dst, void* stream) {
     clear_error();
-    SLAQ_REQUIRE(c && dst && (which == 0 || which == 1), SLAQ_ERR_INVALID_ARG, "bad argument");
-    SLAQ_HIP(hipMemcpyAsync(dst, which == 0 ? c->w : c->grad, c->P * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    SLAQ_REQUIRE(c && dst && which >= 0 && which <= 3, SLAQ_ERR_INVALID_ARG, "bad argument");
+    const float* src[4] = {c->w, c->grad, c->m1, c->m2};
+    SLAQ_HIP(hipMemcpyAsync(dst, src[which], c->P * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return SLAQ_OK;
+}
+
+slaq_status slaq_closure_get_step(slaq_closure_t c, int* step) {
+    clear_error();
+    SLAQ_REQUIRE(c && step, SLAQ_ERR_INVALID_ARG, "bad argument");
+    *step = c->step;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_closure_set_optimizer(slaq_closure_t c, const float* m1, const float* m2, int step, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(c && m1 && m2 && step >= 0, SLAQ_ERR_INVALID_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    SLAQ_HIP(hipMemcpyAsync(c->m1, m1, c->P * 4, hipMemcpyDeviceToDevice, st));
+    SLAQ_HIP(hipMemcpyAsync(c->m2, m2, c->P * 4, hipMemcpyDeviceToDevice, st));
+    c->step = step;
     return SLAQ_OK;
 }
 

@@ -74,6 +74,8 @@ SIGNATURES = {
     "slaq_closure_workspace": [_vp, _i64, ctypes.POINTER(_sz)],
     "slaq_closure_get": [_vp, _int, _vp, _vp],
     "slaq_closure_set": [_vp, _vp, _int, _vp],
+    "slaq_closure_get_step": [_vp, _vp],
+    "slaq_closure_set_optimizer": [_vp, _vp, _vp, _int, _vp],
     "slaq_closure_forward": [_vp, _vp, _i64, _vp, _vp, _sz, _vp],
     "slaq_closure_train_step": [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _sz, _vp],
     "slaq_closure_rules": [_vp, _vp, _vp, _i64, _int, _int, _vp, _vp, _vp, _vp, _vp],
@@ -504,13 +506,32 @@ class Closure:
         return self._ws
 
     def get(self, which=0, stream=None):
+        """0 weights, 1 gradients of the last train step, 2 / 3 Adam moments."""
         out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
         _check(lib().slaq_closure_get(self.handle, which, _ptr(out), _stream(stream)))
         return out
 
+    def _vector(self, v, name):
+        _dev(v, torch.float32, name)
+        if v.numel() != self.n_params:
+            raise ValueError(f"{name} must hold {self.n_params} values, got {v.numel()}")
+        return v
+
     def set(self, params, reset_optimizer=True, stream=None):
-        _dev(params, torch.float32, "params")
+        self._vector(params, "params")
         _check(lib().slaq_closure_set(self.handle, _ptr(params), 1 if reset_optimizer else 0, _stream(stream)))
+
+    def step(self):
+        """Adam steps taken so far."""
+        s = ctypes.c_int()
+        _check(lib().slaq_closure_get_step(self.handle, ctypes.byref(s)))
+        return s.value
+
+    def set_optimizer(self, m1, m2, step, stream=None):
+        """Restores the Adam moments and step count."""
+        self._vector(m1, "m1")
+        self._vector(m2, "m2")
+        _check(lib().slaq_closure_set_optimizer(self.handle, _ptr(m1), _ptr(m2), int(step), _stream(stream)))
 
     def layers(self, vec=None):
         """[(W, b)] views of a parameter vector (default: the weights)."""

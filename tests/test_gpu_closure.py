@@ -160,3 +160,28 @@ def test_batched_probe_data_matches_graph_by_graph():
     for name in ("q5", "q_hi", "qr"):
         a, b = getattr(d_b, name).cpu().numpy(), getattr(d_p, name).cpu().numpy()
         np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-9, err_msg=name)
+
+
+def test_checkpoint_resume_matches_uninterrupted(tmp_path):
+    # 2 epochs, checkpoint, a fresh handle from the file, 2 more epochs: the
+    # same losses and the same weights and Adam state, bit for bit, as 4
+    # epochs in one run (fixed-order reductions; per-epoch sample orders)
+    print("\n[gpu] closure checkpoint / resume", flush=True)
+    tt = torch.from_numpy(T).cuda()
+    d = C.probe_data(closure_graphs(40, seed=5), nv=20, t=tt, seed=50)
+    kw = dict(batch=256, lr=2e-3, seed=7)
+    full = S.Closure(d_in=10, hidden=256, nt=256, seed=11)
+    h_full = C.train(full, d, epochs=4, **kw)
+    part = S.Closure(d_in=10, hidden=256, nt=256, seed=11)
+    ck = tmp_path / "closure.ckpt"
+    h1 = C.train(part, d, epochs=2, checkpoint=str(ck), **kw)
+    steps_at_2 = part.step()
+    del part
+    net, head = C.load_checkpoint(str(ck))
+    assert head["epoch"] == 2 and net.step() == steps_at_2 > 0
+    h2 = C.train(net, d, epochs=2, first_epoch=head["epoch"], **kw)
+    assert h1 + h2 == h_full
+    assert net.step() == full.step()
+    for which in (0, 2, 3):
+        assert torch.equal(net.get(which), full.get(which)), which
+
