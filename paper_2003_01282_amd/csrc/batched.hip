@@ -30,6 +30,7 @@
 namespace slaq {
 
 constexpr double kBatchEpsBreakdown = 1e-6;
+constexpr int kRedSlots = 128;  // doubles of first-level probe sums
 constexpr int kBatchUnroll = 4;  // nonzeros of a row gathered per round
 
 __device__ __forceinline__ uint64_t bmix64(uint64_t seed, uint64_t counter) {
@@ -57,7 +58,7 @@ struct BatchArgs {
 
 // LDS layout (bytes), n_max nodes, ld = 4F floats per node
 struct BatchLds {
-    size_t r, dinv, st, red, coef, total;
+    size_t r, dinv, st, red, red2, coef, total;
 };
 
 __host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int B) {
@@ -72,6 +73,8 @@ __host__ __device__ inline BatchLds batch_lds(int n_max, int nv, int B) {
     off += (size_t)nv * 40;
     L.red = off;
     off += (size_t)B * 4 * 8;
+    L.red2 = off;  // first-level sums of the partials (reduce_chunks)
+    off += (size_t)(nv > kRedSlots ? nv : kRedSlots) * 8;  // K nv <= max(kRedSlots, nv)
     L.coef = off;  // float sigma[4F], tau[4F], a[4F]
     off += (size_t)3 * 4 * F * 4;
     L.total = (off + 15) / 16 * 16;
@@ -97,14 +100,40 @@ __device__ __forceinline__ void init_probe_state(int t, int B, int nv, int F, in
     }
 }
 
-// alpha_j of probe t (t < nv) from the block's FP64 partial dot products
-// red[4 u + c] (threads u = q, q + F, ..., fixed order); writes gal[t m + j-1]
-// (0 once the probe has stopped) and the FP32 update coefficient a_j.
-__device__ __forceinline__ void finish_alpha(int t, int F, int bact, int m, int j, const double* red, double* pst,
-                                             float* coef, double* gal) {
-    const int qq = t >> 2, cc = t & 3;
+// chunks per probe of the first-level sums
+__device__ __forceinline__ int red_chunks(int nv) {
+    const int k = kRedSlots / nv;
+    return k < 1 ? 1 : (k > 8 ? 8 : k);
+}
+
+// First level of the per-probe sums of the block's FP64 partials red[4 u + c]
+// (threads u = q, q + F, ... hold probe 4 q + c): chunk k of probe p adds the
+// row groups k, k + K, ... in order into red2[k nv + p], all chunks of all
+// probes at once; the finish_* calls add the K chunks in order after a barrier.
+__device__ __forceinline__ void reduce_chunks(int t, int B, int F, int bact, int nv, const double* red,
+                                              double* red2) {
+    const int K = red_chunks(nv), R = bact / F;
+    for (int x = t; x < nv * K; x += B) {
+        const int p = x % nv, k = x / nv, qq = p >> 2, cc = p & 3;
+        double s = 0.0;
+        for (int r = k; r < R; r += K) s += red[4 * (r * F + qq) + cc];
+        red2[k * nv + p] = s;
+    }
+}
+
+__device__ __forceinline__ double chunk_sum(int t, int nv, const double* red2) {
+    const int K = red_chunks(nv);
     double s = 0.0;
-    for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
+    for (int k = 0; k < K; ++k) s += red2[k * nv + t];
+    return s;
+}
+
+// alpha_j of probe t (t < nv) from the first-level sums red2 (reduce_chunks);
+// writes gal[t m + j-1] (0 once the probe has stopped) and the FP32 update
+// coefficient a_j.
+__device__ __forceinline__ void finish_alpha(int t, int nv, int m, int j, const double* red2, double* pst, int F,
+                                             float* coef, double* gal) {
+    const double s = chunk_sum(t, nv, red2);
     if (pst[5 * t + 3] != 0.0) {
         const double alpha = pst[5 * t + 0] * s;
         gal[t * m + j - 1] = alpha;
@@ -118,11 +147,9 @@ __device__ __forceinline__ void finish_alpha(int t, int F, int bact, int m, int 
 
 // beta_j = ||R_{j+1}|| of probe t, the breakdown test and the next step's
 // sigma and tau; writes gbe[t m + j-1] (0 once the probe has stopped).
-__device__ __forceinline__ void finish_beta(int t, int F, int bact, int m, int j, const double* red, double* pst,
+__device__ __forceinline__ void finish_beta(int t, int nv, int m, int j, const double* red2, double* pst, int F,
                                             float* coef, double* gbe) {
-    const int qq = t >> 2, cc = t & 3;
-    double s = 0.0;
-    for (int u = qq; u < bact; u += F) s += red[4 * u + cc];
+    const double s = chunk_sum(t, nv, red2);
     if (pst[5 * t + 3] == 0.0) {
         gbe[t * m + j - 1] = 0.0;
         return;
@@ -156,6 +183,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
     float* dinv = (float*)(lds + L.dinv);
     double* pst = (double*)(lds + L.st);  // [nv][5]: sigma, tau, a, active, steps
     double* red = (double*)(lds + L.red);
+    double* red2 = (double*)(lds + L.red2);
     float* coef = (float*)(lds + L.coef);  // [3][4F]
     __shared__ int s_job;
     __shared__ double s_scal[4];
@@ -283,7 +311,9 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s1[c];
             __syncthreads();
-            if (t < a.nv) finish_alpha(t, F, bact, a.m, j, red, pst, coef, gal);
+            reduce_chunks(t, B, F, bact, a.nv, red, red2);
+            __syncthreads();
+            if (t < a.nv) finish_alpha(t, a.nv, a.m, j, red2, pst, F, coef, gal);
             __syncthreads();
             // ---- R_{j+1} = w - a R_j (in place); partial ||R_{j+1}||^2 ---------
             const float4 av = make_float4(coef[8 * F + 4 * q], coef[8 * F + 4 * q + 1], coef[8 * F + 4 * q + 2],
@@ -311,7 +341,9 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s2[c];
             __syncthreads();
-            if (t < a.nv) finish_beta(t, F, bact, a.m, j, red, pst, coef, gbe);
+            reduce_chunks(t, B, F, bact, a.nv, red, red2);
+            __syncthreads();
+            if (t < a.nv) finish_beta(t, a.nv, a.m, j, red2, pst, F, coef, gbe);
             __syncthreads();
         }
 
@@ -335,6 +367,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
     const BatchLds L = batch_lds(0, a.nv, B);
     double* pst = (double*)(lds + L.st);
     double* red = (double*)(lds + L.red);
+    double* red2 = (double*)(lds + L.red2);
     float* coef = (float*)(lds + L.coef);
     __shared__ int s_job;
     __shared__ double s_scal[4];
@@ -454,7 +487,9 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s1[c];
             __syncthreads();
-            if (t < a.nv) finish_alpha(t, F, bact, a.m, j, red, pst, coef, gal);
+            reduce_chunks(t, B, F, bact, a.nv, red, red2);
+            __syncthreads();
+            if (t < a.nv) finish_alpha(t, a.nv, a.m, j, red2, pst, F, coef, gal);
             __syncthreads();
             const float4 av = make_float4(coef[8 * F + 4 * q], coef[8 * F + 4 * q + 1], coef[8 * F + 4 * q + 2],
                                           coef[8 * F + 4 * q + 3]);
@@ -479,7 +514,9 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[4 * t + c] = s2[c];
             __syncthreads();
-            if (t < a.nv) finish_beta(t, F, bact, a.m, j, red, pst, coef, gbe);
+            reduce_chunks(t, B, F, bact, a.nv, red, red2);
+            __syncthreads();
+            if (t < a.nv) finish_beta(t, a.nv, a.m, j, red2, pst, F, coef, gbe);
             __syncthreads();
             float4* const tmp = X;  // X_{j+1} now lives in P; X_j becomes the previous block
             X = P;
