@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
     double* red2 = (double*)(lds + L.red2);
     float* coef = (float*)(lds + L.coef);  // [3][4F]
     __shared__ int s_job;
-    __shared__ double s_scal[4];
+    __shared__ int s_nz;  // non-isolated nodes of the graph: tr L (exact integer sum)
 
     const int t = threadIdx.x;
     const int bact = (B / F) * F;  // threads with a fixed quad
@@ -196,7 +196,10 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
     const int rstride = bact / F;
 
     for (;;) {
-        if (t == 0) s_job = atomicAdd(a.queue, 1);
+        if (t == 0) {
+            s_job = atomicAdd(a.queue, 1);
+            s_nz = 0;
+        }
         __syncthreads();
         const int job = s_job;
         if (job >= a.count) break;
@@ -213,7 +216,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
             dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
             nonzero += d > 0 ? 1 : 0;
         }
-        red[t] = (double)nonzero;
+        atomicAdd(&s_nz, nonzero);
         // ---- probes R_1 = v (graph-local ids, seed + g), stored as X_1 = D^-1/2 v
         //      on rows with edges --------------------------------------------------
         const uint64_t sg = a.seeds ? a.seeds[g] : a.seed + (uint64_t)g;
@@ -235,12 +238,6 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
         // a probe has stopped)
         double* const gal = a.alpha + (int64_t)g * a.nv * a.m;
         double* const gbe = a.beta + (int64_t)g * a.nv * a.m;
-        __syncthreads();
-        if (t == 0) {
-            double s = 0.0;
-            for (int i = 0; i < B; ++i) s += red[i];
-            s_scal[0] = s;  // tr L of the normalized Laplacian
-        }
         __syncthreads();
 
         float4 prev[IPT], wv[IPT];
@@ -348,7 +345,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
         }
 
         if (t < a.nv) a.steps[(int64_t)g * a.nv + t] = (int32_t)pst[5 * t + 4];
-        if (t == 0) a.trace[g] = s_scal[0];
+        if (t == 0) a.trace[g] = (double)s_nz;  // tr L of the normalized Laplacian
         __syncthreads();
     }
 }
@@ -370,7 +367,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
     double* red2 = (double*)(lds + L.red2);
     float* coef = (float*)(lds + L.coef);
     __shared__ int s_job;
-    __shared__ double s_scal[4];
+    __shared__ int s_nz;  // non-isolated nodes of the graph: tr L (exact integer sum)
 
     const int t = threadIdx.x;
     const int bact = (B / F) * F;
@@ -382,7 +379,10 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
     float* const dinv = wsd + (int64_t)blockIdx.x * slot_n;
 
     for (;;) {
-        if (t == 0) s_job = atomicAdd(a.queue, 1);
+        if (t == 0) {
+            s_job = atomicAdd(a.queue, 1);
+            s_nz = 0;
+        }
         __syncthreads();
         const int job = s_job;
         if (job >= a.count) break;
@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
             dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
             nonzero += d > 0 ? 1 : 0;
         }
-        red[t] = (double)nonzero;
+        atomicAdd(&s_nz, nonzero);
         const uint64_t sg = a.seeds ? a.seeds[g] : a.seed + (uint64_t)g;
         for (int64_t x = t; x < (int64_t)n * F; x += B) {
             const int i = (int)(x / F), qq = (int)(x % F), p0 = 4 * qq;
@@ -423,12 +423,6 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
         init_probe_state(t, B, a.nv, F, a.m, 1.0 / sqrt((double)n), pst, coef);
         double* const gal = a.alpha + (int64_t)g * a.nv * a.m;
         double* const gbe = a.beta + (int64_t)g * a.nv * a.m;
-        __syncthreads();
-        if (t == 0) {
-            double s = 0.0;
-            for (int i = 0; i < B; ++i) s += red[i];
-            s_scal[0] = s;
-        }
         __syncthreads();
 
         for (int j = 1; j <= a.m; ++j) {
@@ -523,7 +517,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
             P = tmp;
         }
         if (t < a.nv) a.steps[(int64_t)g * a.nv + t] = (int32_t)pst[5 * t + 4];
-        if (t == 0) a.trace[g] = s_scal[0];
+        if (t == 0) a.trace[g] = (double)s_nz;  // tr L of the normalized Laplacian
         __syncthreads();
     }
 }
