@@ -433,12 +433,25 @@ def union_device(graphs):
     nnz_off = np.concatenate([[0], np.cumsum(nnz)]).astype(np.int64)
     if node_off[-1] > 2**31 - 1:
         raise SlaqError(SLAQ_ERR_INVALID_ARG, "a union needs fewer than 2^31 nodes")
-    shift_c = torch.repeat_interleave(torch.from_numpy(node_off[:-1]).to(dev), torch.from_numpy(nnz).to(dev))
-    ci = (torch.cat(cis).to(torch.int64) + shift_c).to(torch.int32)
-    shift_r = torch.repeat_interleave(torch.from_numpy(nnz_off[:-1]).to(dev), torch.from_numpy(n).to(dev))
-    rp = torch.cat([torch.cat([r[:-1] for r in rps]) + shift_r,
-                    torch.tensor([int(nnz_off[-1])], dtype=torch.int64, device=dev)])
-    return rp, ci, node_off
+    G, N, E = len(graphs), int(node_off[-1]), int(nnz_off[-1])
+    # every global id is below 2^31 (checked above): the shift is added in int32,
+    # in place on the concatenated copy
+    ci = torch.cat(cis)
+    if ci.dtype != torch.int32:
+        ci = ci.to(torch.int32)
+    ci += torch.repeat_interleave(torch.from_numpy(node_off[:-1].astype(np.int32)).to(dev),
+                                  torch.from_numpy(nnz).to(dev), output_size=E)
+    # row pointers: all G arrays concatenated (n_g + 1 entries each) and
+    # shifted by their graph's nonzero offset; global node i of graph g sits at
+    # position i + g, and the union's closing entry is the last one
+    full = torch.cat(rps)
+    full += torch.repeat_interleave(torch.from_numpy(nnz_off[:-1]).to(dev), torch.from_numpy(n + 1).to(dev),
+                                    output_size=N + G)
+    pos = torch.arange(N + 1, dtype=torch.int64, device=dev)
+    pos[:N] += torch.repeat_interleave(torch.arange(G, dtype=torch.int64, device=dev), torch.from_numpy(n).to(dev),
+                                       output_size=N)
+    pos[N] = N + G - 1
+    return full[pos], ci, node_off
 
 
 def batch_run(b, seed, t=None, heat=True, vnge=True, ritz=False, coeffs=False, graph=False, out=None,
