@@ -74,7 +74,12 @@ struct BuildPartial {
 // are tunable (slaq_graph_set_schedule); these are the defaults and bounds.
 constexpr int kDefaultHeavyMin = 128;
 constexpr int kDefaultPiece = 128;
-constexpr int kMinHeavyMin = 128;
+// below SLAQ_RELABEL_MIN_NNZ stored entries the SpMM does not fill the chip and
+// its time is the serial gather chain of the longest light row: shorter light
+// rows, more pieces (Chung-Lu 10^4: 1.39 -> 0.96 ms per step)
+constexpr int kSmallHeavyMin = 32;
+constexpr int kSmallPiece = 64;
+constexpr int kMinHeavyMin = 32;
 constexpr int kMinPiece = 64;
 // Heavy rows are also cut at kColRanges column-id boundaries of equal nnz
 // mass; the pieces of range x are reduced by workgroups b with b % 8 == x,

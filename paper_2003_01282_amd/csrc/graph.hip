@@ -571,8 +571,9 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->scanbuf = (long long*)(base + SL.off_bsum);
     g->trace_part = (double*)(base + SL.off_tpart);
     g->max_heavy = SL.max_heavy;
-    g->heavy_min = kDefaultHeavyMin;
-    g->piece = kDefaultPiece;
+    const bool small = nnz < (int64_t)SLAQ_RELABEL_MIN_NNZ;
+    g->heavy_min = small ? kSmallHeavyMin : kDefaultHeavyMin;
+    g->piece = small ? kSmallPiece : kDefaultPiece;
     g->tile_quads = 0;
     g->precision = laplacian == SLAQ_LAP_COMBINATORIAL ? SLAQ_PREC_FP64 : SLAQ_PREC_FP32;
     g->n = n;
