@@ -807,8 +807,15 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
         // them soonest (1024 threads: 80 ms against 97 at 512 for 2,000 graphs
         // of 1e3 to 1e5 nodes, nv = 20, m = 5)
         int block = c.global ? 1024 : (c.n_hi <= 64 ? 128 : (c.n_hi <= 256 ? 256 : 512));
-        if (bucket_blocks && bidx < n_buckets_cfg && bucket_blocks[bidx] > 0) block = bucket_blocks[bidx];
+        const bool forced = bucket_blocks && bidx < n_buckets_cfg && bucket_blocks[bidx] > 0;
+        if (forced) block = bucket_blocks[bidx];
         slaq_status s = configure_bucket(c, nv, block);
+        // a default size too small for the probe count (one thread per probe
+        // finishes the sums) or for the bucket's rows: the next larger one
+        for (int wider = block * 2; s != SLAQ_OK && !forced && wider <= 1024; wider *= 2) {
+            s = configure_bucket(c, nv, wider);
+            if (s == SLAQ_OK) clear_error();
+        }
         if (s != SLAQ_OK) {
             delete b;
             return s;
