@@ -32,7 +32,7 @@ def mixed(seed):
     return gs
 
 
-@pytest.mark.parametrize("nv", [20, 6, 100, 160])  # 160: more probes than first-level sum slots
+@pytest.mark.parametrize("nv", [20, 6, 100, 160, 256])  # 160, 256: more probes than first-level sum slots; 256 the maximum
 def test_global_buckets_against_plain_path_and_oracle(nv):
     print(f"\n[gpu] batched global buckets nv={nv}", flush=True)
     gs = mixed(5)
