@@ -107,7 +107,7 @@ def test_degenerate_graphs(case):
     np.testing.assert_allclose(gpu["tau2"].sum(axis=1), 1.0, atol=1e-9)
 
 
-@pytest.mark.parametrize("heavy_min,piece", [(128, 64), (256, 512), (128, 1024), (100000, 64)])
+@pytest.mark.parametrize("heavy_min,piece", [(32, 64), (64, 128), (128, 64), (256, 512), (128, 1024), (100000, 64)])
 def test_row_schedules(heavy_min, piece):
     # every schedule computes the same recurrence; heavy rows with partial
     # pieces, rows just below / above the threshold, no heavy rows at all
