@@ -107,3 +107,30 @@ def test_caller_workspace():
     small = inputs.small_graph_mix(20, seed=4)
     u2, o2 = inputs.disjoint_union(small)
     assert S.batch_plan(u2, o2, nv=20, m=6, nt=T.size).workspace_bytes() == 0
+
+
+def test_long_recurrence_lds_and_global():
+    # m = 40 (the eigensolve's wide-m configuration), graphs in an LDS bucket
+    # and in the global one; no breakdown on these sizes, so step counts match
+    print("\n[gpu] batched m=40", flush=True)
+    gs = [inputs.chung_lu(n, 4 * n, 2.4, seed=n) for n in (300, 900, 3000)]
+    union, off = inputs.disjoint_union(gs)
+    nv, m, seed = 12, 40, 5
+    b = S.batch_plan(union, off, nv=nv, m=m, nt=T.size)
+    kinds = b.buckets()
+    assert any(k["in_lds"] for k in kinds) and any(not k["in_lds"] for k in kinds)
+    t = torch.from_numpy(T).cuda()
+    out = {k: v.cpu().numpy() for k, v in S.batch_run(b, seed, t, heat=True, vnge=True, coeffs=True).items()}
+    for g, csr in enumerate(gs):
+        rp, ci = S.to_device(csr)
+        a, be, st = S.lanczos(S.build_graph(rp, ci), nv, m, seed + g)
+        th, w2 = S.ritz(a, be, st)
+        heat = S.signature(th, w2, csr.n, t).cpu().numpy()
+        assert np.array_equal(out["steps"][g], st.cpu().numpy()), g
+        np.testing.assert_allclose(out["heat"][g], heat, rtol=1e-4, err_msg=f"graph {g}")
+        og = O.build_graph(csr.n, csr.row_ptr, csr.col_idx)
+        oa, ob, os_ = O.lanczos(og, nv, m, seed + g)
+        oth, ow2 = O.ritz(oa, ob, os_)
+        oh = O.heat_trace(oth, ow2, csr.n, T)
+        assert (np.abs(out["heat"][g] - oh) / np.abs(oh)).max() <= TOL_HEAT_REL, g
+        np.testing.assert_allclose(out["alpha"][g, :, :3], oa[:, :3], rtol=1e-5, atol=1e-6)
