@@ -123,8 +123,9 @@ slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* tr
  * nonzeros that separate waves reduce in parallel; the pieces of column range
  * x run on workgroups b with b % 8 == x, i.e. one XCD, so that XCD's L2 holds
  * only that range's rows (defaults 128 and 128, or 32 and 64 for graphs of
- * fewer than SLAQ_RELABEL_MIN_NNZ stored entries; heavy_min >= 32, piece a
- * multiple of 64 and >= 64).  Setting it rebuilds the piece plan on `stream`; query
+ * fewer than SLAQ_RELABEL_MIN_NNZ stored entries; heavy_min >= 128, >= 32 for
+ * those graphs, which is what their scratch is sized for; piece a multiple of
+ * 64 and >= 64).  Setting it rebuilds the piece plan on `stream`; query
  * slaq_lanczos_workspace again afterwards, its size depends on the schedule.
  * slaq_graph_schedule reports the schedule and (waiting for the stream of the
  * build) the number of heavy rows and pieces; any pointer may be NULL. */

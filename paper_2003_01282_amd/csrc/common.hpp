@@ -79,7 +79,13 @@ constexpr int kDefaultPiece = 128;
 // rows, more pieces (Chung-Lu 10^4: 1.39 -> 0.96 ms per step)
 constexpr int kSmallHeavyMin = 32;
 constexpr int kSmallPiece = 64;
-constexpr int kMinHeavyMin = 32;
+// lowest heavy_min a schedule may set: it sizes the heavy-row scratch
+// (nnz / bound rows), so small graphs get the low bound they default to and
+// large ones keep their scratch at nnz / 128
+constexpr int kMinHeavyMin = 128;
+inline int heavy_min_bound(int64_t nnz) {
+    return nnz < (int64_t)SLAQ_RELABEL_MIN_NNZ ? kSmallHeavyMin : kMinHeavyMin;
+}
 constexpr int kMinPiece = 64;
 // Heavy rows are also cut at kColRanges column-id boundaries of equal nnz
 // mass; the pieces of range x are reduced by workgroups b with b % 8 == x,

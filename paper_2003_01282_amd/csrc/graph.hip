@@ -409,7 +409,7 @@ struct ScratchLayout {
 static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     ScratchLayout L{};
     L.nplan = (n + kPlanBlock - 1) / kPlanBlock;
-    L.max_heavy = nnz / kMinHeavyMin;
+    L.max_heavy = nnz / heavy_min_bound(nnz);
     if (L.max_heavy > n) L.max_heavy = n;
     L.sort_chunks = (n + kSortChunk - 1) / kSortChunk;
     size_t off = 0;
@@ -648,7 +648,8 @@ slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* tr
 slaq_status slaq_graph_set_schedule(slaq_graph_t g, int heavy_min, int piece, void* stream) {
     clear_error();
     SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
-    SLAQ_REQUIRE(heavy_min >= kMinHeavyMin, SLAQ_ERR_INVALID_ARG, "heavy_min must be >= %d", kMinHeavyMin);
+    SLAQ_REQUIRE(heavy_min >= heavy_min_bound(g->nnz), SLAQ_ERR_INVALID_ARG, "heavy_min must be >= %d",
+                 heavy_min_bound(g->nnz));
     SLAQ_REQUIRE(piece >= kMinPiece && piece % 64 == 0, SLAQ_ERR_INVALID_ARG,
                  "piece must be a multiple of 64 and >= %d", kMinPiece);
     g->heavy_min = heavy_min;

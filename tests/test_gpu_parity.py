@@ -284,3 +284,24 @@ def test_argument_errors_before_launch():
     with pytest.raises(S.SlaqError) as e:
         S.lanczos(g, 4, 5, 1, workspace=small)
     assert e.value.status == 4
+
+
+def test_schedule_defaults_and_bounds_follow_graph_size():
+    # below 2^22 stored entries: heavy rows from 32 nonzeros, pieces of 64,
+    # and the scratch sized for that; above: 128 / 128 and heavy_min >= 128
+    header("schedule bounds by size")
+    csr = inputs.chung_lu(10_000, 50_000, 2.5, seed=4)
+    g = S.build_graph(*S.to_device(csr))
+    sch = g.schedule()
+    assert (sch["heavy_min"], sch["piece"]) == (32, 64)
+    with pytest.raises(S.SlaqError):
+        g.set_schedule(16, 64)
+    g.set_schedule(32, 128)
+    rp, ci = inputs.rmat_device(19, seed=3)
+    assert ci.numel() >= S.SLAQ_RELABEL_MIN_NNZ
+    big = S.build_graph(rp, ci)
+    sch = big.schedule()
+    assert (sch["heavy_min"], sch["piece"]) == (128, 128)
+    with pytest.raises(S.SlaqError):
+        big.set_schedule(64, 128)
+    big.set_schedule(256, 128)
