@@ -49,7 +49,7 @@ typedef enum {
     SLAQ_ERR_NUMERIC = 3,       /* weight <= 0 or not finite (SLAQ_FLAG_CHECK) */
     SLAQ_ERR_WORKSPACE = 4,     /* workspace smaller than the size query says */
     SLAQ_ERR_HIP = 5,           /* a HIP runtime call failed */
-    SLAQ_ERR_UNSUPPORTED = 6,   /* valid request this build does not serve */
+    SLAQ_ERR_UNSUPPORTED = 6,   /* valid request the library does not serve */
     SLAQ_ERR_BAD_CSR = 7        /* SLAQ_FLAG_CHECK: row_ptr / col_idx malformed */
 } slaq_status;
 
@@ -71,7 +71,7 @@ enum { SLAQ_RELABEL_MIN_NNZ = 1 << 22 };
  * products, alpha, beta and everything after them are FP64 either way. */
 enum { SLAQ_PREC_FP32 = 0, SLAQ_PREC_FP64 = 1 };
 
-/* Size limits of this build. */
+/* Size limits of the library. */
 enum { SLAQ_MAX_PROBES = 4096, SLAQ_MAX_STEPS = 64 };
 
 typedef struct slaq_graph_s* slaq_graph_t;

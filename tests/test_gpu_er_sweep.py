@@ -3,7 +3,7 @@ of SLQ against the exact spectrum (a) at n = 1000 over the density and (b)
 over n at average degree 10, with the paper's defaults nv = 100, s = 10.  The
 paper's claim checked here is that the error neither grows with the size nor
 with the density; its comparison systems (linear interpolation, FINGER) are
-not part of this build.  VNGE on L = D - A (the paper's density matrix,
+not implemented here.  VNGE on L = D - A (the paper's density matrix,
 FP64 vectors), the heat signature on the normalized Laplacian (relative l2
 over the 256 time scales, the paper's error metric)."""
 import numpy as np
