@@ -68,3 +68,4 @@ def test_traffic_scaling(tmp_path):
     assert rec["bytes_per_launch"] == stage
     assert rec["update_bytes_per_launch"] == 50 * 1024 * 2 + 40 * 1024
     assert rec["digest"] == P.kernel_sources_digest()
+
