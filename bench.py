@@ -346,22 +346,6 @@ def bench_closure(args):
     print(json.dumps(out_line), flush=True)
 
 
-def line_probe():
-    """Random 128-B-line read rate for working sets of 2 MiB to 16 GiB (the
-    ceiling of gathers that miss L2), from libslaq_probe.so."""
-    import ctypes
-    lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2003_01282_amd",
-                                   "libslaq_probe.so"))
-    mib = [2, 8, 16, 32, 64, 128, 256, 512, 1024, 4096, 8192, 16384]
-    sizes = (ctypes.c_size_t * len(mib))(*[x << 20 for x in mib])
-    out = (ctypes.c_double * len(mib))()
-    rc = lib.slaq_line_probe(sizes, len(mib), out)
-    if rc != 0:
-        raise SystemExit(f"slaq_line_probe failed: hipError {rc}")
-    print(json.dumps({"probe": "random 128-byte line reads", "unit": "TB/s",
-                      "working_set_MiB": mib, "rate": [round(v, 3) for v in out]}), flush=True)
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,11 +366,7 @@ def main():
                     help="time replays of one step captured into a HIP graph (launch-bound workloads)")
     ap.add_argument("--permute", action="store_true",
                     help="rename the nodes of a host-generated graph by a seeded random permutation first")
-    ap.add_argument("--line-probe", action="store_true",
-                    help="only measure random 128-byte-line read throughput against working-set size")
     args = ap.parse_args()
-    if args.line_probe:
-        return line_probe()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the probe sharding across GPUs is a design, not built",
               file=sys.stderr)

@@ -21,6 +21,7 @@ Readings where the paper is silent or inconsistent (each is repeated where used)
   * breakdown: stop when beta_j <= eps_bd * S with S the spectral bound of §2
     (2 for the normalized Laplacian, 2 max_i D_ii for the combinatorial one).
 """
+import warnings
 from dataclasses import dataclass
 
 import numpy as np
@@ -39,18 +40,23 @@ EPS_BREAKDOWN = 1e-6
 @dataclass
 class Graph:
     n: int
-    A: sp.csr_matrix          # symmetric adjacency, float64
+    A: object                 # symmetric adjacency: scipy CSR, or torch CPU CSR (large graphs), float64
     deg: np.ndarray           # D_ii, float64[n]
     dinv: np.ndarray          # D_ii^-1/2, 0 for isolated nodes
     kind: int
+    self_w: np.ndarray = None  # A_ii (self-loop weights), float64[n]
 
     @property
     def trace(self):
-        """tr(L): the number of non-isolated nodes for the normalized
-        Laplacian (each such diagonal entry is 1), sum_i D_ii for L = D - A."""
+        """tr(L), the sum of the Laplacian's diagonal (§2): L_ii = 1 - A_ii / D_ii
+        on a non-isolated node of the normalized Laplacian (0 on an isolated
+        one), L_ii = D_ii - A_ii for L = D - A.  Without self-loops this is the
+        number of non-isolated nodes, or sum_i D_ii."""
+        a = np.zeros(self.n) if self.self_w is None else self.self_w
         if self.kind == NORMALIZED:
-            return float(np.count_nonzero(self.deg > 0))
-        return float(self.deg.sum())
+            pos = self.deg > 0
+            return float(np.sum(1.0 - a[pos] / self.deg[pos]))
+        return float(np.sum(self.deg - a))
 
     @property
     def n_isolated(self):
@@ -64,20 +70,62 @@ class Graph:
         return 2.0 * float(self.deg.max()) if self.n else 0.0
 
 
-def build_graph(n, row_ptr, col_idx, weights=None, kind=NORMALIZED):
+def _row_sums(n, row_ptr, col_idx, w, chunk=1 << 22):
+    """D_ii = sum_j A_ij and A_ii of a CSR, rows taken in chunks (no n x n or
+    nnz-sized index arrays at once)."""
+    deg = np.zeros(n)
+    diag = np.zeros(n)
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        k0, k1 = int(row_ptr[r0]), int(row_ptr[r1])
+        rows = np.repeat(np.arange(r0, r1, dtype=np.int64), np.diff(row_ptr[r0:r1 + 1]))
+        ww = np.ones(k1 - k0) if w is None else np.asarray(w[k0:k1], dtype=np.float64)
+        deg[r0:r1] = np.bincount(rows - r0, weights=ww, minlength=r1 - r0)
+        on = np.asarray(col_idx[k0:k1], dtype=np.int64) == rows
+        diag[r0:r1] = np.bincount(rows[on] - r0, weights=ww[on], minlength=r1 - r0)
+    return deg, diag
+
+
+def build_graph(n, row_ptr, col_idx, weights=None, kind=NORMALIZED, backend="scipy"):
     """CSR (row_ptr[n+1], col_idx[nnz], optional positive weights) -> Graph.
 
-    Degrees follow §2: D_ii = sum_j A_ij (self-loops are taken literally)."""
+    Degrees follow §2: D_ii = sum_j A_ij (self-loops are taken literally).
+    backend "scipy" keeps A as a scipy CSR matrix; "torch" as a torch CPU CSR
+    tensor (int32 indices when nnz < 2^31), whose matrix product uses every
+    host core -- for graphs of billions of entries.  The arithmetic is the same
+    (an FP64 product of A with a block)."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
-    col_idx = np.asarray(col_idx, dtype=np.int64)
     nnz = int(row_ptr[-1])
-    w = np.ones(nnz) if weights is None else np.asarray(weights, dtype=np.float64)
-    A = sp.csr_matrix((w, col_idx, row_ptr), shape=(n, n))
-    deg = np.asarray(A.sum(axis=1)).ravel()
+    if backend == "scipy":
+        col_idx = np.asarray(col_idx, dtype=np.int64)
+        w = np.ones(nnz) if weights is None else np.asarray(weights, dtype=np.float64)
+        A = sp.csr_matrix((w, col_idx, row_ptr), shape=(n, n))
+        deg = np.asarray(A.sum(axis=1)).ravel()
+        self_w = np.asarray(A.diagonal(), dtype=np.float64)
+    elif backend == "torch":
+        import torch
+        deg, self_w = _row_sums(n, row_ptr, col_idx, weights)
+        it = torch.int32 if nnz < 2**31 - 1 else torch.int64
+        vals = (torch.ones(nnz, dtype=torch.float64) if weights is None
+                else torch.from_numpy(np.asarray(weights, dtype=np.float64)))
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")  # torch marks its CSR layout as beta
+            A = torch.sparse_csr_tensor(torch.from_numpy(row_ptr).to(it),
+                                        torch.from_numpy(np.asarray(col_idx)).to(it), vals, size=(n, n))
+    else:
+        raise ValueError(f"unknown backend {backend}")
     dinv = np.zeros(n)
     pos = deg > 0
     dinv[pos] = 1.0 / np.sqrt(deg[pos])
-    return Graph(n=n, A=A, deg=deg, dinv=dinv, kind=kind)
+    return Graph(n=n, A=A, deg=deg, dinv=dinv, kind=kind, self_w=self_w)
+
+
+def _product(A, X):
+    """A X for the adjacency A (scipy or torch CSR) and a dense FP64 block X."""
+    if sp.issparse(A):
+        return A @ X
+    import torch
+    return (A @ torch.from_numpy(np.ascontiguousarray(X))).numpy()
 
 
 def apply_laplacian(g, X):
@@ -89,8 +137,8 @@ def apply_laplacian(g, X):
     if g.kind == NORMALIZED:
         nonisolated = (g.deg > 0).astype(np.float64)
         scaled = g.dinv[:, None] * X
-        return nonisolated[:, None] * X - g.dinv[:, None] * (g.A @ scaled)
-    return g.deg[:, None] * X - g.A @ X
+        return nonisolated[:, None] * X - g.dinv[:, None] * _product(g.A, scaled)
+    return g.deg[:, None] * X - _product(g.A, X)
 
 
 # --------------------------------------------------------------------------
@@ -112,21 +160,23 @@ def splitmix64(seed, counter):
     return z ^ (z >> np.uint64(31))
 
 
-def rademacher(n, nv, seed, node_ids=None):
+def rademacher(n, nv, seed, node_ids=None, columns=None):
     """Probe block V (n x nv) with entries +-1.
 
     Entry (i, p) is bit (p mod 64) of splitmix64(seed, 64*i + p div 64): a set
     bit gives -1.  Keys use the node id, so a probe does not depend on how the
-    rows are stored.  `node_ids` selects rows (default all)."""
+    rows are stored.  `node_ids` selects rows (default all); `columns` selects
+    probes (default 0..nv-1), e.g. a few probes of a very large graph."""
     if nv > 4096:
         raise ValueError("nv > 4096")
     ids = np.arange(n, dtype=np.uint64) if node_ids is None else np.asarray(node_ids, dtype=np.uint64)
-    V = np.empty((ids.size, nv))
-    for word in range((nv + 63) // 64):
+    cols = np.arange(nv) if columns is None else np.asarray(columns, dtype=np.int64)
+    V = np.empty((ids.size, cols.size))
+    for word in np.unique(cols // 64):
         z = splitmix64(seed, ids * np.uint64(64) + np.uint64(word))
-        for b in range(min(64, nv - 64 * word)):
-            bit = (z >> np.uint64(b)) & np.uint64(1)
-            V[:, 64 * word + b] = 1.0 - 2.0 * bit.astype(np.float64)
+        for k in np.flatnonzero(cols // 64 == word):
+            bit = (z >> np.uint64(int(cols[k]) % 64)) & np.uint64(1)
+            V[:, k] = 1.0 - 2.0 * bit.astype(np.float64)
     return V
 
 

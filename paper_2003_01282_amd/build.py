@@ -37,26 +37,6 @@ def _compile(src):
     return obj
 
 
-PROBE_SRC = PKG / "probe" / "line_probe.hip"
-PROBE_OUT = PKG / "libslaq_probe.so"
-
-
-def build_probe():
-    """The random-line read diagnostic (a library of its own, outside the SLQ path)."""
-    BUILD.mkdir(exist_ok=True)
-    obj = BUILD / "line_probe.o"
-    r = subprocess.run([HIPCC, *FLAGS, "-c", str(PROBE_SRC), "-o", str(obj)], capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {PROBE_SRC.name}:\n{r.stdout}\n{r.stderr}")
-    tmp = PROBE_OUT.with_suffix(".so.tmp")
-    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), str(obj)],
-                       capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, PROBE_OUT)
-    return PROBE_OUT
-
-
 def build(verbose=False):
     BUILD.mkdir(exist_ok=True)
     sources = sorted(CSRC.glob("*.hip"))
@@ -69,9 +49,8 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
-    build_probe()
     if verbose:
-        print(f"built {OUT} and {PROBE_OUT}")
+        print(f"built {OUT}")
     return OUT
 
 

@@ -6,7 +6,7 @@ lists are the edge lists.  The figure prints their von Neumann graph entropy
 (dolphins 3.846, karate 3.154).  This script reads the paper's LaTeX source and
 writes one ``u v`` pair per line; it is run once by hand, never by the tests.
 
-Usage:  python tests/golden/extract_fig1.py /root/reference/PAPER.md
+Usage:  python tests/golden/extract_fig1.py <path to the paper's LaTeX source>
 """
 import re
 import sys

@@ -305,3 +305,145 @@ def test_slq_accuracy_against_exact_spectrum_is_monte_carlo_sized(chung_lu_run):
     est = slq.heat_trace(th, w2, csr.n, t)
     ref = exact.exact_heat(lam, t)
     assert np.linalg.norm(est - ref) / np.linalg.norm(ref) < 2e-2
+
+
+# ------------------------------------------------ self-loops and tr L ------
+def with_self_loops(csr, nodes, weight=1.0):
+    """csr plus a self-loop of the given weight on each of `nodes` (weights
+    returned for every stored entry, 1 elsewhere)."""
+    rows = np.repeat(np.arange(csr.n), np.diff(csr.row_ptr))
+    r = np.r_[rows, nodes]
+    c = np.r_[csr.col_idx, nodes].astype(np.int64)
+    w = np.r_[np.ones(csr.nnz), np.full(len(nodes), weight)]
+    order = np.lexsort((c, r))
+    r, c, w = r[order], c[order], w[order]
+    rp = np.zeros(csr.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=csr.n), out=rp[1:])
+    return inputs.CSR(n=csr.n, row_ptr=rp, col_idx=c.astype(np.int32)), w
+
+
+@pytest.mark.parametrize("kind", [slq.NORMALIZED, slq.COMBINATORIAL])
+def test_trace_is_sum_of_eigenvalues_with_self_loops(kind):
+    # tr L is the sum of the spectrum whatever the diagonal of A holds (§2;
+    # the density matrix L / tr L of §2.1 needs it), and the entropy of the
+    # density matrix from the dense spectrum equals SLQ at m = n on the same
+    # probes (brute-force Hutchinson with that trace)
+    csr, w = with_self_loops(inputs.erdos_renyi(30, 0.15, seed=21), [0, 4, 9, 17], 2.5)
+    g = graph(csr, kind, w)
+    lam = exact.spectrum(g)
+    assert abs(g.trace - lam.sum()) <= 1e-10 * abs(lam.sum())
+    # without the loops' share the trace would be off by a visible amount
+    assert abs(lam.sum() - (np.count_nonzero(g.deg > 0) if kind == slq.NORMALIZED else g.deg.sum())) > 0.1
+    nv, seed = 10, 5
+    a, b, s = slq.lanczos(g, nv, csr.n, seed)
+    th, w2 = slq.ritz(a, b, s)
+    c = lam.sum()
+    ref, _ = exact.hutchinson(g, nv, seed, lambda x: -slq.xlogx(x / c))
+    assert abs(slq.vnge(th, w2, csr.n, g.trace) - ref) <= 1e-10 * abs(ref)
+
+
+def test_torch_backend_equals_scipy_backend():
+    # the two sparse-product primitives give the same recurrence (weights,
+    # self-loops and isolated nodes included)
+    base = inputs.chung_lu(1500, 6000, 2.5, seed=13)
+    csr, w = with_self_loops(base, [3, 50, 700], 0.5)
+    w = w * (1.0 + 0.25 * (np.arange(w.size) % 3 == 0))  # asymmetric would be wrong: keep loops only
+    w[np.repeat(np.arange(csr.n), np.diff(csr.row_ptr)) != csr.col_idx] = 1.0
+    for kind in (slq.NORMALIZED, slq.COMBINATORIAL):
+        g1 = slq.build_graph(csr.n, csr.row_ptr, csr.col_idx, w, kind)
+        g2 = slq.build_graph(csr.n, csr.row_ptr, csr.col_idx, w, kind, backend="torch")
+        assert np.array_equal(g1.deg, g2.deg) and np.array_equal(g1.self_w, g2.self_w)
+        a1, b1, s1 = slq.lanczos(g1, 5, 12, seed=8)
+        a2, b2, s2 = slq.lanczos(g2, 5, 12, seed=8)
+        assert np.array_equal(s1, s2)
+        assert np.allclose(a1, a2, rtol=1e-12, atol=1e-14) and np.allclose(b1, b2, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------- Gauss-Radau companion rule --
+@pytest.mark.parametrize("fixed", [0.0, -0.5])
+def test_radau_rule_has_the_fixed_node_and_degree_2k_exactness(fixed):
+    # a (k+1)-point rule with one prescribed node integrates polynomials of
+    # degree <= 2k exactly; the k-point Gauss rule only up to 2k - 1
+    # (Golub and Meurant; the spectral measure of q is sum_i (phi_i^T q)^2
+    # delta(lambda_i), so the moments are q^T L^j q)
+    csr = inputs.erdos_renyi(40, 0.12, seed=17)
+    g = graph(csr)
+    L = exact.dense_laplacian(g)
+    nv, seed = 3, 6
+    a, b, s = slq.lanczos(g, nv, 6, seed)
+    Q = slq.rademacher(csr.n, nv, seed) / math.sqrt(csr.n)
+    for p in range(nv):
+        for k in (2, 3, 5):
+            assert s[p] > k
+            nodes, weights = radau.radau_rule(a[p], b[p], k, fixed)
+            assert nodes.size == k + 1
+            assert np.min(np.abs(nodes - fixed)) < 1e-10
+            lam, U = np.linalg.eigh(slq.tridiagonal(a[p], b[p], k))
+            gw = U[0] ** 2
+            mom = Q[:, p].copy()
+            for j in range(2 * k + 1):
+                exact_j = Q[:, p] @ mom  # q^T L^j q
+                assert abs(np.sum(weights * nodes ** j) - exact_j) <= 1e-9 * max(1.0, abs(exact_j)), (k, j)
+                gauss_j = np.sum(gw * lam ** j)
+                if j < 2 * k:
+                    assert abs(gauss_j - exact_j) <= 1e-9 * max(1.0, abs(exact_j))
+                else:  # the Gauss rule misses the degree-2k moment
+                    assert abs(gauss_j - exact_j) > 1e-6
+                mom = L @ mom
+
+
+# ------------------------------------------------------ Algorithm 1 entries --
+@pytest.mark.parametrize("kind", [slq.NORMALIZED, slq.COMBINATORIAL])
+def test_algorithm1_entry_points_equal_bruteforce(kind):
+    # SLaQ_LSD and SLaQ_VNGE at m = n equal Hutchinson on the same probes,
+    # heat and wave kept apart (a swapped branch fails)
+    csr = inputs.sbm(36, 3, 0.4, 0.05, seed=2)
+    g = graph(csr, kind)
+    nv, seed = 8, 31
+    t = np.array([0.05, 0.4, 1.7])
+    heat = slq.slaq_lsd(g, nv, csr.n, seed, t)
+    wave = slq.slaq_lsd(g, nv, csr.n, seed, t, wave=True)
+    for k, tt in enumerate(t):
+        h, _ = exact.hutchinson(g, nv, seed, lambda x: np.exp(-tt * x))
+        w, _ = exact.hutchinson(g, nv, seed, lambda x: np.cos(tt * x))
+        assert abs(heat[k] - h) <= 1e-10 * abs(h)
+        assert abs(wave[k] - w) <= 1e-10 * max(abs(w), 1.0)
+        assert abs(heat[k] - wave[k]) > 1e-3
+    c = g.trace
+    H, _ = exact.hutchinson(g, nv, seed, lambda x: -slq.xlogx(x / c))
+    assert abs(slq.slaq_vnge(g, nv, csr.n, seed) - H) <= 1e-10 * abs(H)
+
+
+# ------------------------------------- combinatorial spectral bound / breakdown
+def test_combinatorial_spectral_bound_covers_the_spectrum():
+    # Gershgorin (§2): every eigenvalue of D - A lies in [0, 2 max D_ii]
+    for seed in range(4):
+        csr = inputs.chung_lu(200, 700, 2.5, seed=seed)
+        r = np.repeat(np.arange(csr.n), np.diff(csr.row_ptr))
+        w = 0.5 + ((r + csr.col_idx) % 5)  # symmetric positive weights
+        g = graph(csr, slq.COMBINATORIAL, w)
+        lam = exact.spectrum(g)
+        assert g.spectral_bound == 2.0 * g.deg.max()
+        assert lam.max() <= g.spectral_bound * (1 + 1e-12)
+        assert lam.max() >= 0.5 * g.spectral_bound  # the bound is not loose by more than 2x (lambda_max >= max D)
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e-9, 1e7])
+def test_combinatorial_breakdown_is_scale_invariant(scale):
+    # K_n under D - A has eigenvalues {0, n}: a probe's Krylov space has
+    # dimension <= 2, whatever the weight of the edges; the breakdown test is
+    # relative to the spectral bound 2 max D_ii, so tiny weights do not stop
+    # the recurrence early and large ones still stop it at the Krylov dimension
+    csr = inputs.complete(12)
+    g = graph(csr, slq.COMBINATORIAL, np.full(csr.nnz, scale))
+    nv = 8
+    a, b, s = slq.lanczos(g, nv, 6, seed=4)
+    V = slq.rademacher(csr.n, nv, 4)
+    for p in range(nv):
+        k = distinct_eigenvalues_seen(graph(csr, slq.COMBINATORIAL), V[:, p] / math.sqrt(csr.n))
+        assert k <= 2
+        assert s[p] == k, (p, s[p], k)
+        assert np.all(b[p, : k - 1] > 1e-3 * scale)
+    th, w2 = slq.ritz(a, b, s)
+    assert np.allclose(th[w2 > 1e-12], np.where(th[w2 > 1e-12] > 1e-6 * scale, 12.0 * scale, 0.0),
+                       rtol=1e-9, atol=1e-9 * scale)
