@@ -46,7 +46,8 @@ typedef enum {
     SLAQ_OK = 0,
     SLAQ_ERR_INVALID_ARG = 1,   /* NULL pointer, size out of range, bad enum */
     SLAQ_ERR_NOT_SYMMETRIC = 2, /* SLAQ_FLAG_CHECK found (i,j) without (j,i) */
-    SLAQ_ERR_NUMERIC = 3,       /* weight <= 0 or not finite (SLAQ_FLAG_CHECK) */
+    SLAQ_ERR_NUMERIC = 3,       /* weight <= 0 or not finite (SLAQ_FLAG_CHECK), or a
+                                   device-detected problem (slaq_device_status) */
     SLAQ_ERR_WORKSPACE = 4,     /* workspace smaller than the size query says */
     SLAQ_ERR_HIP = 5,           /* a HIP runtime call failed */
     SLAQ_ERR_UNSUPPORTED = 6,   /* valid request the library does not serve */
@@ -110,9 +111,12 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr,
                              void* scratch, size_t scratch_bytes, void* stream,
                              slaq_graph_t* out);
 
-/* Waits for the build on its stream and reports n, nnz, tr(L) (number of
- * non-isolated nodes, or sum_i D_ii), the isolated-node count and max D_ii.
- * Any output pointer may be NULL. */
+/* Waits for the build (and any later work) on its stream and reports n, nnz,
+ * tr(L) = sum_i L_ii (the number of non-isolated nodes, or sum_i D_ii, less
+ * the self-loops' share A_ii / D_ii, or A_ii), the isolated-node count and
+ * max D_ii.  Any output pointer may be NULL.  Returns SLAQ_ERR_NUMERIC (with
+ * the outputs written) when the graph's last slaq_lanczos run produced a
+ * non-finite coefficient (see slaq_device_status). */
 slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* trace,
                             int64_t* n_isolated, double* max_degree);
 
@@ -243,6 +247,22 @@ slaq_status slaq_signature(const double* theta, const double* tau2, int nv, int 
  * (on the device, no wait); out double[1]. */
 slaq_status slaq_vnge(slaq_graph_t g, const double* theta, const double* tau2, int nv,
                       int m, double* out, void* stream);
+
+/* Algorithm 1 from the Lanczos coefficients: SLaQ_LSD and SLaQ_VNGE with the
+ * eigensolve inside.  slaq_lsd takes alpha, beta, steps as slaq_lanczos
+ * writes them (device, [nv*m], [nv*m], [nv]), solves each T_p (FP64
+ * implicit QR, eq. "quadratic") and writes Gamma_f = n/nv sum_p sum_k
+ * tau2 f(theta) (eq. "slq") for f = exp(-t x) or cos(t x) at the nt times
+ * t[0..nt) into out double[nt]; slaq_vnge_slq writes -n/nv sum tau2
+ * g(theta / trace), g(x) = x ln x (0 for x <= 0), into out double[1], with
+ * the caller's trace = tr L (0 gives 0).  No workspace: every block of
+ * slaq_lsd re-solves the nv tridiagonals for its 32 times (callers that
+ * reuse the Gauss rules call slaq_ritz once and slaq_signature / slaq_vnge).
+ * 1 <= nv <= SLAQ_MAX_PROBES, 1 <= m <= SLAQ_MAX_STEPS, 1 <= nt <= 65535. */
+slaq_status slaq_lsd(const double* alpha, const double* beta, const int32_t* steps, int nv, int m, int64_t n,
+                     const double* t, int nt, int kind, double* out, void* stream);
+slaq_status slaq_vnge_slq(const double* alpha, const double* beta, const int32_t* steps, int nv, int m,
+                          int64_t n, double trace, double* out, void* stream);
 
 /* ---- Batched SLQ over many graphs -------------------------------------
  * A batch is the block-diagonal union of G graphs: node_off[g] .. node_off[g+1]
@@ -377,6 +397,12 @@ slaq_status slaq_closure_gauss_values(const double* theta, const double* tau2, i
 slaq_status slaq_closure_targets(const double* q_hi, const double* q_lo, int64_t total, float* y, void* stream);
 slaq_status slaq_closure_apply(const float* yhat, const double* q5, const double* qr, int n_graphs, int nv, int nt,
                                const int64_t* graph_n, double tol, double* heat, int* flags, void* stream);
+/* Hutchinson's estimate (§3.1, eq. "trace") from per-probe quadratic forms:
+ * heat[g][b] = graph_n[g] / nv sum_p q[g nv + p][b] (probes in order), for
+ * q double[n_graphs nv][nt] (e.g. slaq_closure_gauss_values of the plain
+ * Gauss rules), graph_n int64[n_graphs], heat double[n_graphs][nt]. */
+slaq_status slaq_hutchinson_mean(const double* q, int n_graphs, int nv, int nt, const int64_t* graph_n,
+                                 double* heat, void* stream);
 
 /* Stage timing with HIP events (off by default).  While enabled, every launch
  * of a stage kernel ("spmm_pieces", "spmm_rows", "spmm_heavy", "finalize",
@@ -390,6 +416,21 @@ slaq_status slaq_closure_apply(const float* yhat, const double* q5, const double
 slaq_status slaq_profile_enable(int on);
 slaq_status slaq_profile_reset(void);
 slaq_status slaq_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+
+/* Device-detected numeric problems.  Kernels that find a non-finite Lanczos
+ * coefficient alpha_j or beta_j (§3.1's recurrence; e.g. from a NaN weight
+ * built without SLAQ_FLAG_CHECK) set SLAQ_STATUS_NONFINITE; a tridiagonal
+ * eigensolve of the Gauss rule (§3.1, eq. "quadratic"; Algorithm 1's eigh)
+ * that reaches its sweep cap (60 k implicit QR sweeps for a k x k matrix,
+ * which only non-finite input reaches in practice) sets
+ * SLAQ_STATUS_NO_CONVERGENCE.  The bits of a graph's last slaq_lanczos run
+ * make slaq_graph_info return SLAQ_ERR_NUMERIC (its outputs are still
+ * written).  Every kernel also ORs its bits into one status word per device:
+ * slaq_device_status waits for `stream`, returns the word in *bits (may be
+ * NULL), clears it when clear != 0, and returns SLAQ_ERR_NUMERIC when it was
+ * non-zero.  Work on other streams of the device is not waited for. */
+enum { SLAQ_STATUS_NONFINITE = 1u, SLAQ_STATUS_NO_CONVERGENCE = 2u };
+slaq_status slaq_device_status(unsigned* bits, int clear, void* stream);
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* slaq_last_error(void);

@@ -146,9 +146,9 @@ def probe_data(graphs, nv, t, m_hi=30, mf=5, seed=0, labels=True, batched=True):
 
 
 def heat_from_q(q, graph_n, nv):
-    """n/nv sum over each graph's probes (plain Hutchinson aggregation)."""
-    G = graph_n.numel()
-    return q.view(G, nv, -1).sum(dim=1) * (graph_n.to(torch.float64) / nv)[:, None]
+    """n/nv sum over each graph's probes (Hutchinson's estimate, in the
+    library: slaq_hutchinson_mean)."""
+    return S.hutchinson_mean(q.contiguous(), graph_n, nv)
 
 
 def epoch_seed(seed, epoch):

@@ -53,7 +53,8 @@ struct BatchArgs {
     double* alpha;          // [G][nv][m]
     double* beta;           // [G][nv][m]
     int32_t* steps;         // [G][nv]
-    double* trace;          // [G]: tr L (non-isolated node count)
+    double* trace;          // [G]: tr L
+    unsigned* dstat;        // device status word (SLAQ_STATUS_* bits)
 };
 
 // LDS layout (bytes), n_max nodes, ld = 4F floats per node
@@ -132,10 +133,11 @@ __device__ __forceinline__ double chunk_sum(int t, int nv, const double* red2) {
 // writes gal[t m + j-1] (0 once the probe has stopped) and the FP32 update
 // coefficient a_j.
 __device__ __forceinline__ void finish_alpha(int t, int nv, int m, int j, const double* red2, double* pst, int F,
-                                             float* coef, double* gal) {
+                                             float* coef, double* gal, unsigned* dstat) {
     const double s = chunk_sum(t, nv, red2);
     if (pst[5 * t + 3] != 0.0) {
         const double alpha = pst[5 * t + 0] * s;
+        if (!isfinite(alpha)) raise_status(dstat, SLAQ_STATUS_NONFINITE);
         gal[t * m + j - 1] = alpha;
         pst[5 * t + 2] = alpha * pst[5 * t + 0];
         coef[8 * F + t] = (float)pst[5 * t + 2];
@@ -148,12 +150,13 @@ __device__ __forceinline__ void finish_alpha(int t, int nv, int m, int j, const 
 // beta_j = ||R_{j+1}|| of probe t, the breakdown test and the next step's
 // sigma and tau; writes gbe[t m + j-1] (0 once the probe has stopped).
 __device__ __forceinline__ void finish_beta(int t, int nv, int m, int j, const double* red2, double* pst, int F,
-                                            float* coef, double* gbe) {
+                                            float* coef, double* gbe, unsigned* dstat) {
     const double s = chunk_sum(t, nv, red2);
     if (pst[5 * t + 3] == 0.0) {
         gbe[t * m + j - 1] = 0.0;
         return;
     }
+    if (!isfinite(s)) raise_status(dstat, SLAQ_STATUS_NONFINITE);
     const double b = sqrt(fmax(s, 0.0));
     gbe[t * m + j - 1] = b;
     if (j < m && !(b > kBatchEpsBreakdown * 2.0)) {
@@ -173,6 +176,39 @@ __device__ __forceinline__ void finish_beta(int t, int nv, int m, int j, const d
     }
 }
 
+// Degrees and D^-1/2 of one graph (thread per row), its non-isolated count
+// (LDS integer atomic) and the self-loops' share of tr L (§2: L_ii = 1 -
+// A_ii / D_ii), summed in thread order only when the graph has a loop.  Uses
+// red[0, B) and ends with a barrier.
+__device__ __forceinline__ void degrees_and_loops(int t, int B, int n, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, int64_t base,
+                                                  float* __restrict__ dinv, double* red, int* s_nz, int* s_loops,
+                                                  double* s_corr) {
+    int nonzero = 0, loops = 0;
+    double share = 0.0;
+    for (int i = t; i < n; i += B) {
+        const int64_t s = rp[i], e = rp[i + 1], d = e - s;
+        dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
+        nonzero += d > 0 ? 1 : 0;
+        int self = 0;
+        for (int64_t k = s; k < e; ++k) self += (int64_t)col[k] == base + i ? 1 : 0;
+        if (self) {
+            ++loops;
+            share += (double)self / (double)d;
+        }
+    }
+    atomicAdd(s_nz, nonzero);
+    if (loops) atomicAdd(s_loops, loops);
+    red[t] = share;
+    __syncthreads();
+    if (t == 0) {
+        double c = 0.0;
+        if (*s_loops)
+            for (int b = 0; b < B; ++b) c += red[b];
+        *s_corr = c;
+    }
+}
+
 template <int B, int IPT>
 __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -186,7 +222,9 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
     double* red2 = (double*)(lds + L.red2);
     float* coef = (float*)(lds + L.coef);  // [3][4F]
     __shared__ int s_job;
-    __shared__ int s_nz;  // non-isolated nodes of the graph: tr L (exact integer sum)
+    __shared__ int s_nz;     // non-isolated nodes of the graph (exact integer sum)
+    __shared__ int s_loops;  // rows with a self-loop
+    __shared__ double s_corr;  // self-loops' share of tr L, sum_i A_ii / D_ii
 
     const int t = threadIdx.x;
     const int bact = (B / F) * F;  // threads with a fixed quad
@@ -199,6 +237,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
         if (t == 0) {
             s_job = atomicAdd(a.queue, 1);
             s_nz = 0;
+            s_loops = 0;
         }
         __syncthreads();
         const int job = s_job;
@@ -209,14 +248,8 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
         const int64_t* rp = a.rp + base;
         const int32_t* col = a.col;
 
-        // ---- degrees, D^-1/2, tr L (non-isolated count) ---------------------
-        int nonzero = 0;
-        for (int i = t; i < n; i += B) {
-            const int64_t d = rp[i + 1] - rp[i];
-            dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
-            nonzero += d > 0 ? 1 : 0;
-        }
-        atomicAdd(&s_nz, nonzero);
+        // ---- degrees, D^-1/2, tr L (non-isolated count less the loops' share)
+        degrees_and_loops(t, B, n, rp, col, base, dinv, red, &s_nz, &s_loops, &s_corr);
         // ---- probes R_1 = v (graph-local ids, seed + g), stored as X_1 = D^-1/2 v
         //      on rows with edges --------------------------------------------------
         const uint64_t sg = a.seeds ? a.seeds[g] : a.seed + (uint64_t)g;
@@ -310,7 +343,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
             __syncthreads();
             reduce_chunks(t, B, F, bact, a.nv, red, red2);
             __syncthreads();
-            if (t < a.nv) finish_alpha(t, a.nv, a.m, j, red2, pst, F, coef, gal);
+            if (t < a.nv) finish_alpha(t, a.nv, a.m, j, red2, pst, F, coef, gal, a.dstat);
             __syncthreads();
             // ---- R_{j+1} = w - a R_j (in place); partial ||R_{j+1}||^2 ---------
             const float4 av = make_float4(coef[8 * F + 4 * q], coef[8 * F + 4 * q + 1], coef[8 * F + 4 * q + 2],
@@ -340,12 +373,12 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
             __syncthreads();
             reduce_chunks(t, B, F, bact, a.nv, red, red2);
             __syncthreads();
-            if (t < a.nv) finish_beta(t, a.nv, a.m, j, red2, pst, F, coef, gbe);
+            if (t < a.nv) finish_beta(t, a.nv, a.m, j, red2, pst, F, coef, gbe, a.dstat);
             __syncthreads();
         }
 
         if (t < a.nv) a.steps[(int64_t)g * a.nv + t] = (int32_t)pst[5 * t + 4];
-        if (t == 0) a.trace[g] = (double)s_nz;  // tr L of the normalized Laplacian
+        if (t == 0) a.trace[g] = (double)s_nz - s_corr;  // tr L of the normalized Laplacian
         __syncthreads();
     }
 }
@@ -367,7 +400,9 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
     double* red2 = (double*)(lds + L.red2);
     float* coef = (float*)(lds + L.coef);
     __shared__ int s_job;
-    __shared__ int s_nz;  // non-isolated nodes of the graph: tr L (exact integer sum)
+    __shared__ int s_nz;     // non-isolated nodes of the graph (exact integer sum)
+    __shared__ int s_loops;  // rows with a self-loop
+    __shared__ double s_corr;  // self-loops' share of tr L, sum_i A_ii / D_ii
 
     const int t = threadIdx.x;
     const int bact = (B / F) * F;
@@ -382,6 +417,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
         if (t == 0) {
             s_job = atomicAdd(a.queue, 1);
             s_nz = 0;
+            s_loops = 0;
         }
         __syncthreads();
         const int job = s_job;
@@ -395,13 +431,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
         float4* P = slot + slot_quads;       // X_{j-1}, then X_{j+1}
         float4* W = slot + 2 * slot_quads;   // D^-1/2 w
 
-        int nonzero = 0;
-        for (int i = t; i < n; i += B) {
-            const int64_t d = rp[i + 1] - rp[i];
-            dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
-            nonzero += d > 0 ? 1 : 0;
-        }
-        atomicAdd(&s_nz, nonzero);
+        degrees_and_loops(t, B, n, rp, col, base, dinv, red, &s_nz, &s_loops, &s_corr);
         const uint64_t sg = a.seeds ? a.seeds[g] : a.seed + (uint64_t)g;
         for (int64_t x = t; x < (int64_t)n * F; x += B) {
             const int i = (int)(x / F), qq = (int)(x % F), p0 = 4 * qq;
@@ -483,7 +513,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
             __syncthreads();
             reduce_chunks(t, B, F, bact, a.nv, red, red2);
             __syncthreads();
-            if (t < a.nv) finish_alpha(t, a.nv, a.m, j, red2, pst, F, coef, gal);
+            if (t < a.nv) finish_alpha(t, a.nv, a.m, j, red2, pst, F, coef, gal, a.dstat);
             __syncthreads();
             const float4 av = make_float4(coef[8 * F + 4 * q], coef[8 * F + 4 * q + 1], coef[8 * F + 4 * q + 2],
                                           coef[8 * F + 4 * q + 3]);
@@ -510,14 +540,14 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
             __syncthreads();
             reduce_chunks(t, B, F, bact, a.nv, red, red2);
             __syncthreads();
-            if (t < a.nv) finish_beta(t, a.nv, a.m, j, red2, pst, F, coef, gbe);
+            if (t < a.nv) finish_beta(t, a.nv, a.m, j, red2, pst, F, coef, gbe, a.dstat);
             __syncthreads();
             float4* const tmp = X;  // X_{j+1} now lives in P; X_j becomes the previous block
             X = P;
             P = tmp;
         }
         if (t < a.nv) a.steps[(int64_t)g * a.nv + t] = (int32_t)pst[5 * t + 4];
-        if (t == 0) a.trace[g] = (double)s_nz;  // tr L of the normalized Laplacian
+        if (t == 0) a.trace[g] = (double)s_nz - s_corr;  // tr L of the normalized Laplacian
         __syncthreads();
     }
 }
@@ -929,6 +959,8 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
         a.beta = be;
         a.steps = sp;
         a.trace = b->tr_dev;
+        a.dstat = device_status_word();
+        SLAQ_REQUIRE(a.dstat, SLAQ_ERR_HIP, "device status word unavailable");
         const int grid = std::min(c.grid, a.count);
         if (c.global) {
             const int Fq = (b->nv + 3) / 4;

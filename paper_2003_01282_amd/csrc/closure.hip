@@ -315,7 +315,8 @@ __global__ void __launch_bounds__(256) init_params(int64_t P, uint64_t seed, con
 __global__ void __launch_bounds__(64) probe_rules(int64_t count, const double* __restrict__ alpha,
                                                   const double* __restrict__ beta, const int32_t* __restrict__ steps,
                                                   int ms, int mf, double* __restrict__ th, double* __restrict__ w2,
-                                                  double* __restrict__ thr, double* __restrict__ w2r) {
+                                                  double* __restrict__ thr, double* __restrict__ w2r,
+                                                  unsigned* dstat) {
     const int64_t p = blockIdx.x * 64LL + threadIdx.x;
     if (p >= count) return;
     double d[SLAQ_MAX_STEPS + 1], e[SLAQ_MAX_STEPS + 1], u[SLAQ_MAX_STEPS + 1];
@@ -327,7 +328,7 @@ __global__ void __launch_bounds__(64) probe_rules(int64_t count, const double* _
         d[i] = a[i];
         e[i] = i + 1 < k ? b[i] : 0.0;
     }
-    tridiag_eig_first_row(d, e, u, k, 1);
+    if (tridiag_eig_first_row(d, e, u, k, 1) < 0) raise_status(dstat, SLAQ_STATUS_NO_CONVERGENCE);
     // insertion sort ascending
     for (int i = 1; i < k; ++i) {
         const double x = d[i], y = u[i] * u[i];
@@ -373,7 +374,7 @@ __global__ void __launch_bounds__(64) probe_rules(int64_t count, const double* _
     d[k] = phi;
     e[k - 1] = bk;
     e[k] = 0.0;
-    tridiag_eig_first_row(d, e, u, k + 1, 1);
+    if (tridiag_eig_first_row(d, e, u, k + 1, 1) < 0) raise_status(dstat, SLAQ_STATUS_NO_CONVERGENCE);
     for (int i = 0; i <= mf; ++i) {
         thr[p * (mf + 1) + i] = i <= k ? d[i] : 0.0;
         w2r[p * (mf + 1) + i] = i <= k ? u[i] * u[i] : 0.0;
@@ -445,6 +446,19 @@ __global__ void __launch_bounds__(256) closure_apply(int G, int nv, int nt, cons
     if (bad) atomicOr(&any, 1);
     __syncthreads();
     if (threadIdx.x == 0) flags[g] = any;
+}
+
+// Hutchinson's estimate from per-probe quadratic forms (§3.1, eq. "trace"):
+// heat[g][b] = n_g / nv sum_p Q[g nv + p][b], probes added in order.  One
+// block per graph, threads over the times.
+__global__ void __launch_bounds__(256) hutchinson_mean(int nv, int nt, const double* __restrict__ Q,
+                                                       const int64_t* __restrict__ gn, double* __restrict__ heat) {
+    const int g = blockIdx.x;
+    for (int b = threadIdx.x; b < nt; b += blockDim.x) {
+        double s = 0.0;
+        for (int p = 0; p < nv; ++p) s += Q[((int64_t)g * nv + p) * nt + b];
+        heat[(int64_t)g * nt + b] = (double)gn[g] / nv * s;
+    }
 }
 
 __global__ void __launch_bounds__(256) to_bf16(int64_t n, const float* __restrict__ a, bf16* __restrict__ b) {
@@ -810,8 +824,10 @@ slaq_status slaq_closure_rules(const double* alpha, const double* beta, const in
     SLAQ_REQUIRE(alpha && beta && steps && theta && tau2 && theta_r && tau2_r, SLAQ_ERR_INVALID_ARG, "NULL pointer");
     SLAQ_REQUIRE(count >= 1 && mf >= 1 && mf <= ms && ms <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG,
                  "need count >= 1 and 1 <= mf <= ms <= %d", SLAQ_MAX_STEPS);
+    unsigned* const dstat = device_status_word();
+    SLAQ_REQUIRE(dstat, SLAQ_ERR_HIP, "device status word unavailable");
     hipLaunchKernelGGL(probe_rules, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, (hipStream_t)stream, count,
-                       alpha, beta, steps, ms, mf, theta, tau2, theta_r, tau2_r);
+                       alpha, beta, steps, ms, mf, theta, tau2, theta_r, tau2_r, dstat);
     SLAQ_LAUNCHED();
     return SLAQ_OK;
 }
@@ -855,6 +871,16 @@ slaq_status slaq_closure_apply(const float* yhat, const double* q5, const double
     SLAQ_TIMED("closure_apply", (hipStream_t)stream,
                hipLaunchKernelGGL(closure_apply, dim3(n_graphs), dim3(256), 0, (hipStream_t)stream, n_graphs, nv, nt,
                                   yhat, q5, qr, graph_n, tol, heat, flags));
+    SLAQ_LAUNCHED();
+    return SLAQ_OK;
+}
+
+slaq_status slaq_hutchinson_mean(const double* q, int n_graphs, int nv, int nt, const int64_t* graph_n,
+                                 double* heat, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(q && graph_n && heat, SLAQ_ERR_INVALID_ARG, "NULL pointer argument");
+    SLAQ_REQUIRE(n_graphs >= 1 && nv >= 1 && nt >= 1, SLAQ_ERR_INVALID_ARG, "need n_graphs, nv, nt >= 1");
+    hipLaunchKernelGGL(hutchinson_mean, dim3(n_graphs), dim3(256), 0, (hipStream_t)stream, nv, nt, q, graph_n, heat);
     SLAQ_LAUNCHED();
     return SLAQ_OK;
 }

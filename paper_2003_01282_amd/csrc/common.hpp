@@ -56,8 +56,16 @@ struct GraphStats {
     long long n_pieces;    // total pieces of the heavy rows
     long long n_rows;      // rows of the internal CSR (n_act when relabelled, else n)
     unsigned int check;    // SLAQ_FLAG_CHECK findings (bit mask, see graph.hip)
-    unsigned int pad;
+    unsigned int status;   // SLAQ_STATUS_* bits of this graph's Lanczos runs
 };
+
+// Address of the current device's status word (SLAQ_STATUS_* bits), or NULL
+// if the runtime cannot give it.  Kernels OR into it with raise_status.
+unsigned* device_status_word();
+
+__device__ __forceinline__ void raise_status(unsigned* word, unsigned bits) {
+    if (word) atomicOr(word, bits);
+}
 
 constexpr int kBuildBlocks = 1024;  // grid of the degree kernel (partials size)
 constexpr int kPlanBlock = 256;     // rows per block of the plan kernels
@@ -68,6 +76,9 @@ struct BuildPartial {
     long long nonisolated;
     long long pad;
 };
+
+// Grid of the self-loop pass of the build (one FP64 partial per block).
+constexpr int kLoopBlocks = 1024;
 
 // Row schedule of the SpMM: rows of degree >= heavy_min are cut into pieces of
 // at most `piece` nonzeros (a piece never crosses a row).  heavy_min and piece

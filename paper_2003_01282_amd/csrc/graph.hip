@@ -81,28 +81,84 @@ __global__ void __launch_bounds__(256) degree_kernel(int64_t n, const int64_t* _
     }
 }
 
+// Self-loop share of tr L (§2: L_ii = 1 - A_ii / D_ii on a non-isolated node
+// of the normalized Laplacian, D_ii - A_ii for L = D - A): per block the sum
+// over its rows of A_ii / D_ii, or of A_ii.  A wave takes 64 consecutive rows;
+// each lane scans its own row up to 64 entries, longer rows are scanned by
+// the whole wave in turn (lanes over the entries, fixed-order tree).
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(256) loop_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const float* __restrict__ w,
+                                                   int laplacian, const double* __restrict__ d64,
+                                                   double* __restrict__ part) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc = 0.0;
+    const int64_t nwin = (n + 63) / 64;
+    for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += (int64_t)gridDim.x * 4) {
+        const int64_t i = win * 64 + lane;
+        int64_t s = 0, e = 0;
+        if (i < n) {
+            s = rp[i];
+            e = rp[i + 1];
+        }
+        const bool lng = e - s > 64;
+        double self = 0.0;
+        if (!lng)
+            for (int64_t k = s; k < e; ++k)
+                if ((int64_t)col[k] == i) self += WEIGHTED ? (double)w[k] : 1.0;
+        uint64_t mask = __ballot(lng);
+        while (mask) {
+            const int src = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int64_t rs = __shfl(s, src), re = __shfl(e, src), ri = win * 64 + src;
+            double ps = 0.0;
+            for (int64_t k = rs + lane; k < re; k += 64)
+                if ((int64_t)col[k] == ri) ps += WEIGHTED ? (double)w[k] : 1.0;
+            for (int off = 32; off > 0; off >>= 1) ps += __shfl_down(ps, off);
+            ps = __shfl(ps, 0);
+            if (lane == src) self = ps;
+        }
+        if (i < n && self != 0.0) {
+            const double d = d64[i];  // D^-1/2 or D_ii
+            acc += laplacian == SLAQ_LAP_NORMALIZED ? self * d * d : self;
+        }
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 __global__ void __launch_bounds__(256) stats_kernel(int64_t n, int nparts, int laplacian,
                                                     const BuildPartial* __restrict__ part,
+                                                    const double* __restrict__ loop_part, int nloop,
                                                     GraphStats* __restrict__ st) {
-    __shared__ double smax[256], ssum[256];
+    __shared__ double smax[256], ssum[256], sloop[256];
     __shared__ long long snz[256];
     const int t = threadIdx.x;
-    double dmax = 0.0, dsum = 0.0;
+    double dmax = 0.0, dsum = 0.0, dl = 0.0;
     long long nz = 0;
     for (int b = t; b < nparts; b += 256) {
         dmax = fmax(dmax, part[b].max_degree);
         dsum += part[b].sum_degree;
         nz += part[b].nonisolated;
     }
+    for (int b = t; b < nloop; b += 256) dl += loop_part[b];
     smax[t] = dmax;
     ssum[t] = dsum;
     snz[t] = nz;
+    sloop[t] = dl;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (t < off) {
             smax[t] = fmax(smax[t], smax[t + off]);
             ssum[t] += ssum[t + off];
             snz[t] += snz[t + off];
+            sloop[t] += sloop[t + off];
         }
         __syncthreads();
     }
@@ -110,9 +166,11 @@ __global__ void __launch_bounds__(256) stats_kernel(int64_t n, int nparts, int l
         st->max_degree = smax[0];
         st->sum_degree = ssum[0];
         st->n_isolated = (long long)n - snz[0];
-        st->trace = laplacian == SLAQ_LAP_NORMALIZED ? (double)snz[0] : ssum[0];
+        // tr L = sum_i L_ii: the non-isolated count (or sum_i D_ii) less the self-loops' share
+        st->trace = (laplacian == SLAQ_LAP_NORMALIZED ? (double)snz[0] : ssum[0]) - sloop[0];
         st->n_rows = n;  // the relabelling lowers it to n_act
         st->check = 0u;
+        st->status = 0u;
     }
 }
 
@@ -402,7 +460,7 @@ slaq_status exclusive_scan(const long long* in, int64_t len, int64_t* out, long 
 struct ScratchLayout {
     size_t off_stats, off_part, off_counts, off_hrow, off_hoff, off_bounds, off_segk, off_cnt, off_segoff, off_bsum,
         off_perm, off_inv, off_rp2, off_col2, off_w2, off_tmp, off_diag2, off_d64, off_d64r, off_len, off_sortcnt,
-        off_sortoff, off_tpart, off_choff, off_ccnt, off_coff, total;
+        off_sortoff, off_tpart, off_lpart, off_choff, off_ccnt, off_coff, total;
     int64_t nplan, max_heavy, sort_chunks;
 };
 
@@ -447,6 +505,7 @@ static ScratchLayout scratch_layout(int64_t n, int64_t nnz) {
     L.off_sortcnt = take(sizeof(long long) * sort_len);
     L.off_sortoff = take(sizeof(int64_t) * sort_len);
     L.off_tpart = take(sizeof(double) * 2 * kTraceBlocks);
+    L.off_lpart = take(sizeof(double) * kLoopBlocks);
     L.off_choff = take(sizeof(int64_t) * ((size_t)n + 1));
     L.off_ccnt = take(sizeof(int32_t) * kColRanges * (size_t)relabel_max_chunks(nnz));
     L.off_coff = take(sizeof(int32_t) * kColRanges * (size_t)relabel_max_chunks(nnz));
@@ -553,7 +612,18 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
         hipLaunchKernelGGL(degree_kernel<false>, dim3(blocks), dim3(256), 0, st, n, row_ptr, weights,
                            laplacian, dinv_out, d64, part);
     SLAQ_LAUNCHED();
-    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(256), 0, st, n, blocks, laplacian, part, stats);
+    double* loop_part = (double*)(base + SL.off_lpart);
+    int lblocks = (int)((n + 255) / 256);
+    if (lblocks > kLoopBlocks) lblocks = kLoopBlocks;
+    if (weights)
+        hipLaunchKernelGGL(loop_kernel<true>, dim3(lblocks), dim3(256), 0, st, n, row_ptr, col_idx, weights,
+                           laplacian, d64, loop_part);
+    else
+        hipLaunchKernelGGL(loop_kernel<false>, dim3(lblocks), dim3(256), 0, st, n, row_ptr, col_idx, weights,
+                           laplacian, d64, loop_part);
+    SLAQ_LAUNCHED();
+    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(256), 0, st, n, blocks, laplacian, part, loop_part, lblocks,
+                       stats);
     SLAQ_LAUNCHED();
 
     const bool relabel = (flags & SLAQ_FLAG_RELABEL) ||
@@ -642,6 +712,8 @@ slaq_status slaq_graph_info(slaq_graph_t g, int64_t* n, int64_t* nnz, double* tr
     if (trace) *trace = hs.trace;
     if (n_isolated) *n_isolated = hs.n_isolated;
     if (max_degree) *max_degree = hs.max_degree;
+    SLAQ_REQUIRE(hs.status == 0u, SLAQ_ERR_NUMERIC,
+                 "the last Lanczos run on this graph found a non-finite coefficient (status 0x%x)", hs.status);
     return SLAQ_OK;
 }
 

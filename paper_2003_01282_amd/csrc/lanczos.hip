@@ -167,9 +167,10 @@ template <typename V>
 __global__ void __launch_bounds__(256) state_init(int nv, int m, int ld, double sigma1,
                                                   double* __restrict__ alpha, double* __restrict__ beta,
                                                   int32_t* __restrict__ steps, ProbeState* __restrict__ ps,
-                                                  V* __restrict__ coef) {
+                                                  V* __restrict__ coef, GraphStats* __restrict__ st) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
+    if (t == 0) st->status = 0u;  // this run's findings only
     for (int k = t; k < nv * m; k += stride) {
         alpha[k] = 0.0;
         beta[k] = 0.0;
@@ -591,10 +592,20 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return red[0];
 }
 
+// A non-finite coefficient sets SLAQ_STATUS_NONFINITE in the graph's status
+// and in the device word.
+__device__ __forceinline__ void check_finite(double x, GraphStats* st, unsigned* dstat) {
+    if (!isfinite(x)) {
+        atomicOr(&st->status, (unsigned)SLAQ_STATUS_NONFINITE);
+        raise_status(dstat, SLAQ_STATUS_NONFINITE);
+    }
+}
+
 template <typename V>
 __global__ void __launch_bounds__(256) finalize_a(const double* __restrict__ part, int nb, int ld, int m, int j,
-                                                  const GraphStats* __restrict__ st, ProbeState* __restrict__ ps,
-                                                  double* __restrict__ alpha, V* __restrict__ coef) {
+                                                  GraphStats* __restrict__ st, ProbeState* __restrict__ ps,
+                                                  double* __restrict__ alpha, V* __restrict__ coef,
+                                                  unsigned* dstat) {
     const int p = blockIdx.x;
     const double s1 = sum_partials(part, nb, p);
     if (threadIdx.x != 0) return;
@@ -606,6 +617,7 @@ __global__ void __launch_bounds__(256) finalize_a(const double* __restrict__ par
     // isolated rows: R_j[i] = rho_j v_i, w_i = -tau_{j-1} rho_{j-1} v_i
     const double iso = (double)st->n_isolated * s.rho * (-s.tau * s.rho_prev);
     const double al = s.sigma * (s1 + iso);
+    check_finite(al, st, dstat);
     alpha[(int64_t)p * m + (j - 1)] = al;
     s.a = al * s.sigma;
     ps[p].a = s.a;
@@ -614,9 +626,10 @@ __global__ void __launch_bounds__(256) finalize_a(const double* __restrict__ par
 
 template <typename V>
 __global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ part, int nb, int ld, int m, int j,
-                                                  const GraphStats* __restrict__ st, int laplacian, double eps_bd,
+                                                  GraphStats* __restrict__ st, int laplacian, double eps_bd,
                                                   ProbeState* __restrict__ ps, double* __restrict__ beta,
-                                                  int32_t* __restrict__ steps, V* __restrict__ coef) {
+                                                  int32_t* __restrict__ steps, V* __restrict__ coef,
+                                                  unsigned* dstat) {
     const int p = blockIdx.x;
     const double s2 = sum_partials(part, nb, p);
     if (threadIdx.x != 0) return;
@@ -625,6 +638,7 @@ __global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ par
     const double rho_next = -s.tau * s.rho_prev - s.a * s.rho;
     const double nrm2 = s2 + (double)st->n_isolated * rho_next * rho_next;
     const double be = sqrt(fmax(nrm2, 0.0));
+    check_finite(nrm2, st, dstat);
     beta[(int64_t)p * m + (j - 1)] = be;
     const double bound = laplacian == SLAQ_LAP_NORMALIZED ? 2.0 : 2.0 * st->max_degree;
     if (j < m && !(be > eps_bd * bound)) {
@@ -786,9 +800,12 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
     const int mode = g->laplacian;
     const bool weighted = g->weights != nullptr;
     const V* diag = diag_of<V>(g);
+    unsigned* const dstat = device_status_word();
+    SLAQ_REQUIRE(dstat, SLAQ_ERR_HIP, "device status word unavailable");
 
     const double sigma1 = 1.0 / sqrt((double)g->n);
-    hipLaunchKernelGGL(state_init<V>, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef);
+    hipLaunchKernelGGL(state_init<V>, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef,
+                       g->stats);
     SLAQ_LAUNCHED();
     int rps = 0;
     const int sgrid = sweep_grid(g->n, L.F, &rps);
@@ -833,7 +850,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
         }
         SLAQ_TIMED("finalize", st,
                    hipLaunchKernelGGL(finalize_a<V>, dim3(nv), dim3(256), 0, st, part1, nbp, L.ld, m, j,
-                                      g->stats, ps, alpha, coef));
+                                      g->stats, ps, alpha, coef, dstat));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("update", st,
                    hipLaunchKernelGGL(update<V>, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->stats,
@@ -842,7 +859,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
                    hipLaunchKernelGGL(finalize_b<V>, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,
-                                      g->stats, mode, kEpsBreakdown, ps, beta, steps, coef));
+                                      g->stats, mode, kEpsBreakdown, ps, beta, steps, coef, dstat));
         SLAQ_LAUNCHED();
         if (j < m) {
             const int t = cur;

@@ -27,6 +27,9 @@ SLAQ_CV_FITTED = 2
 SLAQ_MAX_PROBES = 4096
 SLAQ_MAX_STEPS = 64
 SLAQ_ERR_INVALID_ARG = 1
+SLAQ_ERR_NUMERIC = 3
+SLAQ_STATUS_NONFINITE = 1
+SLAQ_STATUS_NO_CONVERGENCE = 2
 
 STATUS = {
     0: "SLAQ_OK", 1: "SLAQ_ERR_INVALID_ARG", 2: "SLAQ_ERR_NOT_SYMMETRIC", 3: "SLAQ_ERR_NUMERIC",
@@ -83,6 +86,10 @@ SIGNATURES = {
     "slaq_closure_gauss_values": [_vp, _vp, _i64, _int, _int, _vp, _int, _vp, _vp],
     "slaq_closure_targets": [_vp, _vp, _i64, _vp, _vp],
     "slaq_closure_apply": [_vp, _vp, _vp, _int, _int, _int, _vp, ctypes.c_double, _vp, _vp, _vp],
+    "slaq_lsd": [_vp, _vp, _vp, _int, _int, _i64, _vp, _int, _int, _vp, _vp],
+    "slaq_vnge_slq": [_vp, _vp, _vp, _int, _int, _i64, ctypes.c_double, _vp, _vp],
+    "slaq_device_status": [ctypes.POINTER(ctypes.c_uint), _int, _vp],
+    "slaq_hutchinson_mean": [_vp, _int, _int, _int, _vp, _vp, _vp],
     "slaq_profile_enable": [_int],
     "slaq_profile_reset": [],
     "slaq_profile_read": [ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
@@ -295,6 +302,45 @@ def vnge(g, theta, tau2, out=None, stream=None):
         out = torch.empty(1, dtype=torch.float64, device=theta.device)
     _check(lib().slaq_vnge(g.handle, _ptr(theta), _ptr(tau2), nv, m, _ptr(out), _stream(stream)))
     return out
+
+
+def lsd(alpha, beta, steps, n, t, kind=SLAQ_SIG_HEAT, out=None, stream=None):
+    """slaq_lsd (Algorithm 1's SLaQ_LSD from the Lanczos coefficients, the
+    eigensolve inside) -> double[nt]."""
+    nv, m = alpha.shape
+    _dev(alpha, torch.float64, "alpha")
+    _dev(beta, torch.float64, "beta")
+    _dev(steps, torch.int32, "steps")
+    _dev(t, torch.float64, "t")
+    if out is None:
+        out = torch.empty(t.numel(), dtype=torch.float64, device=alpha.device)
+    _check(lib().slaq_lsd(_ptr(alpha), _ptr(beta), _ptr(steps), nv, m, n, _ptr(t), t.numel(), kind, _ptr(out),
+                          _stream(stream)))
+    return out
+
+
+def vnge_slq(alpha, beta, steps, n, trace, out=None, stream=None):
+    """slaq_vnge_slq (Algorithm 1's SLaQ_VNGE from the Lanczos coefficients
+    and tr L) -> double[1]."""
+    nv, m = alpha.shape
+    _dev(alpha, torch.float64, "alpha")
+    _dev(beta, torch.float64, "beta")
+    _dev(steps, torch.int32, "steps")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=alpha.device)
+    _check(lib().slaq_vnge_slq(_ptr(alpha), _ptr(beta), _ptr(steps), nv, m, n, float(trace), _ptr(out),
+                               _stream(stream)))
+    return out
+
+
+def device_status(clear=True, stream=None):
+    """slaq_device_status: waits for the stream and returns the current
+    device's SLAQ_STATUS_* bits (0 = nothing found), clearing them if asked."""
+    bits = ctypes.c_uint()
+    st = lib().slaq_device_status(ctypes.byref(bits), 1 if clear else 0, _stream(stream))
+    if st not in (0, SLAQ_ERR_NUMERIC):
+        _check(st)
+    return bits.value
 
 
 def graph_traces(g, out=None, stream=None):
@@ -626,6 +672,17 @@ def closure_apply(yhat, q5, qr, graph_n, nv, tol, stream=None):
     _check(lib().slaq_closure_apply(_ptr(yhat), _ptr(q5), _ptr(qr), G, nv, nt, _ptr(graph_n), ctypes.c_double(tol),
                                     _ptr(heat), _ptr(flags), _stream(stream)))
     return heat, flags
+
+
+def hutchinson_mean(q, graph_n, nv, stream=None):
+    """slaq_hutchinson_mean -> heat [G][nt] = n_g / nv sum over graph g's probes."""
+    G = graph_n.numel()
+    nt = q.shape[-1]
+    _dev(q, torch.float64, "q")
+    _dev(graph_n, torch.int64, "graph_n")
+    heat = torch.empty((G, nt), dtype=torch.float64, device=q.device)
+    _check(lib().slaq_hutchinson_mean(_ptr(q), G, nv, nt, _ptr(graph_n), _ptr(heat), _stream(stream)))
+    return heat
 
 
 def profile_enable(on=True):

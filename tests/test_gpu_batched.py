@@ -111,3 +111,34 @@ def test_autotune_keeps_results():
     assert all(c[0] in (128, 256, 512, 1024) for c in choice)
     after = S.batch_run(b, 5, t)["heat"].cpu().numpy()
     np.testing.assert_allclose(after, before, rtol=1e-6)
+
+
+def with_loops(csr, nodes):
+    r = np.r_[np.repeat(np.arange(csr.n), np.diff(csr.row_ptr)), nodes]
+    c = np.r_[csr.col_idx.astype(np.int64), nodes]
+    o = np.lexsort((c, r))
+    rp = np.zeros(csr.n + 1, dtype=np.int64)
+    np.add.at(rp, r[o] + 1, 1)
+    return inputs.CSR(n=csr.n, row_ptr=np.cumsum(rp), col_idx=c[o].astype(np.int32))
+
+
+def test_batched_self_loops_trace():
+    # graphs with self-loops in the LDS and in the global bucket: VNGE divides
+    # by tr L = sum_i (1 - A_ii / D_ii) (§2, §2.1), as the oracle does
+    print("\n[gpu] batched graphs with self-loops", flush=True)
+    gs = [with_loops(inputs.erdos_renyi(60, 0.1, seed=1), [0, 5, 9]),
+          inputs.erdos_renyi(50, 0.1, seed=2),
+          with_loops(inputs.sbm(300, 3, 0.3, 0.02, seed=3), [1, 2, 299]),
+          with_loops(inputs.chung_lu(6000, 24000, 2.5, seed=4), [0, 10, 5999])]
+    union, off = inputs.disjoint_union(gs)
+    b = S.batch_plan(union, off, nv=20, m=10, nt=T.size)
+    assert any(not bk["in_lds"] for bk in b.buckets())
+    t = torch.from_numpy(T).cuda()
+    out = S.batch_run(b, 55, t, heat=True, vnge=True)
+    H = out["vnge"].cpu().numpy()
+    for g, csr in enumerate(gs):
+        og = O.build_graph(csr.n, csr.row_ptr, csr.col_idx)
+        a, be, st = O.lanczos(og, 20, 10, 55 + g)
+        th, w2 = O.ritz(a, be, st)
+        oH = O.vnge(th, w2, csr.n, og.trace)
+        assert abs(H[g] - oH) <= TOL_VNGE_REL * abs(oH), (g, H[g], oH)

@@ -305,3 +305,38 @@ def test_schedule_defaults_and_bounds_follow_graph_size():
     with pytest.raises(S.SlaqError):
         big.set_schedule(64, 128)
     big.set_schedule(256, 128)
+
+
+def loop_graph(n=600, pairs=2500, loops=(0, 3, 17, 250), weight=None, seed=6):
+    """Chung-Lu graph with self-loops on `loops` (symmetric by construction)."""
+    csr = inputs.chung_lu(n, pairs, 2.4, seed=seed)
+    r = np.r_[np.repeat(np.arange(csr.n), np.diff(csr.row_ptr)), list(loops)]
+    c = np.r_[csr.col_idx.astype(np.int64), list(loops)]
+    o = np.lexsort((c, r))
+    rp = np.zeros(csr.n + 1, dtype=np.int64)
+    np.add.at(rp, r[o] + 1, 1)
+    out = inputs.CSR(n=csr.n, row_ptr=np.cumsum(rp), col_idx=c[o].astype(np.int32))
+    w = None
+    if weight is not None:
+        w = np.ones(out.nnz, dtype=np.float32)
+        rr = np.repeat(np.arange(out.n), np.diff(out.row_ptr))
+        w[rr == out.col_idx] = weight
+    return out, w
+
+
+@pytest.mark.parametrize("lap", [S.SLAQ_LAP_NORMALIZED, S.SLAQ_LAP_COMBINATORIAL])
+@pytest.mark.parametrize("weight", [None, 3.5])
+def test_self_loops_trace_and_vnge(lap, weight):
+    # tr L is the sum of L's diagonal (§2), so self-loops lower it; the
+    # density matrix of §2.1 divides by it.  The build's trace equals the sum
+    # of the dense spectrum, and VNGE matches the oracle's
+    header(f"self-loops lap={lap} weight={weight}")
+    from oracle import exact
+    csr, w = loop_graph(weight=weight)
+    gpu = gpu_run(csr, 16, 15, 5, T256, laplacian=lap, weights=w, check=True)
+    ora = oracle_run(csr, 16, 15, 5, T256, laplacian=lap, weights=None if w is None else w.astype(np.float64))
+    lam = exact.spectrum(ora["graph"])
+    assert abs(gpu["info"]["trace"] - lam.sum()) <= 1e-6 * lam.sum()
+    assert abs(ora["graph"].trace - lam.sum()) <= 1e-9 * lam.sum()
+    assert np.array_equal(gpu["steps"], ora["steps"])
+    assert_signature_parity(gpu, ora, csr.n, f"self-loops lap={lap}")
