@@ -21,6 +21,12 @@ def test_lsd_and_vnge_from_coefficients(nv, m, nt):
     csr = inputs.chung_lu(1200, 5000, 2.5, seed=12)
     rp, ci = S.to_device(csr)
     g = S.build_graph(rp, ci)
+    if m > 15:
+        # beyond the FP32 configurations (m = 15) the FP32 recurrence, run
+        # without reorthogonalization, drifts from the FP64 one (ghost Ritz
+        # values), and cos(t theta) at t = 100 magnifies that drift t-fold:
+        # the long recurrences compare with FP64 vectors
+        g.set_precision(S.SLAQ_PREC_FP64)
     a, b, s = S.lanczos(g, nv, m, seed=77)
     t = O.t_grid(nt) if nt > 1 else np.array([0.3])
     tt = torch.from_numpy(t).cuda()
