@@ -226,6 +226,20 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
                          double* beta, int32_t* steps, void* workspace,
                          size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): slaq_lanczos
+ * with its workspace taken from a library-owned device array of
+ * SLAQ_NOALLOC_WORKSPACE_BYTES (64 MiB) per GPU, held until the process ends.
+ * Same arguments, kernels and results as slaq_lanczos (bit for bit).  Returns
+ * SLAQ_ERR_WORKSPACE, with nothing enqueued, when slaq_lanczos_workspace()
+ * for this graph and nv exceeds that size.  Calls no allocating routine
+ * (with slaq_profile_enable on, the stage timer creates HIP events).  All calls on one GPU share the array:
+ * calls that overlap on a GPU (other streams, other threads) race, so the
+ * caller orders them. */
+#define SLAQ_NOALLOC_WORKSPACE_BYTES (64u << 20)
+slaq_status slaq_lanczos_noalloc(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha,
+                                 double* beta, int32_t* steps, void* stream);
+
 /* Gauss nodes and weights (§3.1, eq. "quadratic"): theta[p*m+k] are the
  * eigenvalues of T_p (size steps[p]) and tau2[p*m+k] the squared first
  * components of its normalized eigenvectors; entries k >= steps[p] are 0.

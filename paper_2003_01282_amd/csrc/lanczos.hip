@@ -44,6 +44,8 @@
 // rho (v[i]^2 = 1) and the isolated-node count.
 #include <cmath>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "profile.hpp"
 
@@ -870,6 +872,28 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
     return SLAQ_OK;
 }
 
+// Workspace of slaq_lanczos_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in symbol): it takes the
+// device's address from hipGetSymbolAddress once per device, with that device
+// current, and uses that address everywhere.
+__device__ __align__(256) unsigned char scratch[SLAQ_NOALLOC_WORKSPACE_BYTES];
+
+static void* noalloc_workspace() {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
 }  // namespace slaq
 
 using namespace slaq;
@@ -900,6 +924,31 @@ slaq_status slaq_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, double* a
     if (g->precision == SLAQ_PREC_FP64)
         return run_lanczos<double>(g, nv, m, seed, alpha, beta, steps, workspace, workspace_bytes, st);
     return run_lanczos<float>(g, nv, m, seed, alpha, beta, steps, workspace, workspace_bytes, st);
+}
+
+slaq_status slaq_lanczos_noalloc(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha, double* beta,
+                                 int32_t* steps, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    SLAQ_REQUIRE(alpha && beta && steps, SLAQ_ERR_INVALID_ARG, "alpha, beta and steps must be non-NULL");
+    SLAQ_REQUIRE(nv >= 1 && nv <= SLAQ_MAX_PROBES, SLAQ_ERR_INVALID_ARG, "nv must be in [1, %d]",
+                 SLAQ_MAX_PROBES);
+    SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
+    const size_t need =
+        g->precision == SLAQ_PREC_FP64 ? make_layout<double>(g, nv).total : make_layout<float>(g, nv).total;
+    SLAQ_REQUIRE(need <= (size_t)SLAQ_NOALLOC_WORKSPACE_BYTES, SLAQ_ERR_WORKSPACE,
+                 "this graph and probe count need %zu bytes of workspace; the library's own is %zu bytes "
+                 "(use slaq_lanczos with a caller workspace)",
+                 need, (size_t)SLAQ_NOALLOC_WORKSPACE_BYTES);
+    void* ws = noalloc_workspace();
+    SLAQ_REQUIRE(ws, SLAQ_ERR_HIP, "library workspace unavailable on the current device");
+    hipStream_t st = (hipStream_t)stream;
+    // every kernel writes what it later reads (state_init the per-probe state
+    // and coefficients, probe_init the first block, each block its partials):
+    // nothing in the workspace has to start at zero
+    if (g->precision == SLAQ_PREC_FP64)
+        return run_lanczos<double>(g, nv, m, seed, alpha, beta, steps, ws, SLAQ_NOALLOC_WORKSPACE_BYTES, st);
+    return run_lanczos<float>(g, nv, m, seed, alpha, beta, steps, ws, SLAQ_NOALLOC_WORKSPACE_BYTES, st);
 }
 
 }  // extern "C"

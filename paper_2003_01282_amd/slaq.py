@@ -28,6 +28,7 @@ SLAQ_MAX_PROBES = 4096
 SLAQ_MAX_STEPS = 64
 SLAQ_ERR_INVALID_ARG = 1
 SLAQ_ERR_NUMERIC = 3
+SLAQ_ERR_WORKSPACE = 4
 SLAQ_STATUS_NONFINITE = 1
 SLAQ_STATUS_NO_CONVERGENCE = 2
 
@@ -60,6 +61,7 @@ SIGNATURES = {
                             ctypes.POINTER(_i64)],
     "slaq_lanczos_workspace": [_vp, _int, _int, ctypes.POINTER(_sz)],
     "slaq_lanczos": [_vp, _int, _int, ctypes.c_uint64, _vp, _vp, _vp, _vp, _sz, _vp],
+    "slaq_lanczos_noalloc": [_vp, _int, _int, ctypes.c_uint64, _vp, _vp, _vp, _vp],
     "slaq_ritz": [_vp, _vp, _vp, _int, _int, _vp, _vp, _vp],
     "slaq_signature": [_vp, _vp, _int, _int, _i64, _vp, _int, _int, _vp, _vp],
     "slaq_vnge": [_vp, _vp, _vp, _int, _int, _vp, _vp],
@@ -267,6 +269,23 @@ def lanczos(g, nv, m, seed, workspace=None, out=None, stream=None):
     alpha, beta, steps = out
     _check(lib().slaq_lanczos(g.handle, nv, m, ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(alpha), _ptr(beta),
                               _ptr(steps), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return alpha, beta, steps
+
+
+NOALLOC_WORKSPACE_BYTES = 64 << 20
+
+
+def lanczos_noalloc(g, nv, m, seed, out=None, stream=None):
+    """slaq_lanczos_noalloc: slaq_lanczos on the library's own workspace (no
+    device allocation by the library) -> (alpha, beta, steps)."""
+    dev = g._keep["row_ptr"].device
+    if out is None:
+        out = (torch.empty((nv, m), dtype=torch.float64, device=dev),
+               torch.empty((nv, m), dtype=torch.float64, device=dev),
+               torch.empty(nv, dtype=torch.int32, device=dev))
+    alpha, beta, steps = out
+    _check(lib().slaq_lanczos_noalloc(g.handle, nv, m, ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(alpha),
+                                      _ptr(beta), _ptr(steps), _stream(stream)))
     return alpha, beta, steps
 
 
