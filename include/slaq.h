@@ -87,6 +87,10 @@ slaq_status slaq_graph_scratch_bytes(int64_t n, int64_t nnz, size_t* bytes);
  *             the normalized Laplacian, D_ii for the combinatorial one.
  *   scratch   device memory of slaq_graph_scratch_bytes(); holds tr(L), the
  *             number of isolated nodes and max_i D_ii.
+ * CSR: row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing, row_ptr[n] =
+ * nnz), col_idx int32[nnz] in [0, n), each row's columns ascending without
+ * repeats (the self-loop entry A_ii is found by binary search), weights
+ * float[nnz] > 0 or NULL for 1; the pattern and weights symmetric.
  * The handle stores the pointers it was given: row_ptr, col_idx, weights,
  * dinv_out and scratch must stay valid and unchanged until
  * slaq_graph_destroy.  With SLAQ_FLAG_CHECK the call validates the CSR

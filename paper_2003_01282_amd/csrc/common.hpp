@@ -78,7 +78,7 @@ struct BuildPartial {
 };
 
 // Grid of the self-loop pass of the build (one FP64 partial per block).
-constexpr int kLoopBlocks = 1024;
+constexpr int kLoopBlocks = 4096;
 
 // Row schedule of the SpMM: rows of degree >= heavy_min are cut into pieces of
 // at most `piece` nonzeros (a piece never crosses a row).  heavy_min and piece

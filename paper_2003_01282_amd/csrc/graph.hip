@@ -83,42 +83,27 @@ __global__ void __launch_bounds__(256) degree_kernel(int64_t n, const int64_t* _
 
 // Self-loop share of tr L (§2: L_ii = 1 - A_ii / D_ii on a non-isolated node
 // of the normalized Laplacian, D_ii - A_ii for L = D - A): per block the sum
-// over its rows of A_ii / D_ii, or of A_ii.  A wave takes 64 consecutive rows;
-// each lane scans its own row up to 64 entries, longer rows are scanned by
-// the whole wave in turn (lanes over the entries, fixed-order tree).
+// over its rows of A_ii / D_ii, or of A_ii.  A thread per row (grid-stride)
+// finds column i in its row by binary search: rows list their columns in
+// ascending order without repeats (the CSR contract SLAQ_FLAG_CHECK
+// verifies), so a row costs about log2(length) loads and hub rows no more
+// than a few dozen.
 template <bool WEIGHTED>
 __global__ void __launch_bounds__(256) loop_kernel(int64_t n, const int64_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const float* __restrict__ w,
                                                    int laplacian, const double* __restrict__ d64,
                                                    double* __restrict__ part) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double acc = 0.0;
-    const int64_t nwin = (n + 63) / 64;
-    for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += (int64_t)gridDim.x * 4) {
-        const int64_t i = win * 64 + lane;
-        int64_t s = 0, e = 0;
-        if (i < n) {
-            s = rp[i];
-            e = rp[i + 1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = rp[i], e = rp[i + 1];
+        int64_t lo = s, hi = e;  // first entry with column >= i
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)col[mid] < i) lo = mid + 1;
+            else hi = mid;
         }
-        const bool lng = e - s > 64;
-        double self = 0.0;
-        if (!lng)
-            for (int64_t k = s; k < e; ++k)
-                if ((int64_t)col[k] == i) self += WEIGHTED ? (double)w[k] : 1.0;
-        uint64_t mask = __ballot(lng);
-        while (mask) {
-            const int src = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const int64_t rs = __shfl(s, src), re = __shfl(e, src), ri = win * 64 + src;
-            double ps = 0.0;
-            for (int64_t k = rs + lane; k < re; k += 64)
-                if ((int64_t)col[k] == ri) ps += WEIGHTED ? (double)w[k] : 1.0;
-            for (int off = 32; off > 0; off >>= 1) ps += __shfl_down(ps, off);
-            ps = __shfl(ps, 0);
-            if (lane == src) self = ps;
-        }
-        if (i < n && self != 0.0) {
+        if (lo < e && (int64_t)col[lo] == i) {
+            const double self = WEIGHTED ? (double)w[lo] : 1.0;
             const double d = d64[i];  // D^-1/2 or D_ii
             acc += laplacian == SLAQ_LAP_NORMALIZED ? self * d * d : self;
         }
