@@ -148,6 +148,17 @@ slaq_status slaq_graph_schedule(slaq_graph_t g, int* heavy_min, int* piece, int6
  * Changes the workspace size. */
 slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads);
 
+/* Hot window of the SpMM gathers on a relabelled graph: the first `rows`
+ * labels of each of the 8 column ranges (the range's highest-degree rows)
+ * are gathered with ordinary loads, every other row, the column indices and
+ * the piece partials with the non-temporal hint, so that the hottest probe
+ * rows keep the last-level cache.  -1 (default) = automatic: the window whose
+ * probe rows fill 200 MB (65,536 rows per range at nv = 100 in FP32).  A
+ * window of at least n caches every gather; graphs that are not relabelled
+ * always do.  Storage hints only: results are identical for every value. */
+slaq_status slaq_graph_set_cache_rows(slaq_graph_t g, int64_t rows);
+slaq_status slaq_graph_cache_rows(slaq_graph_t g, int64_t* rows);
+
 /* Precision of the Lanczos vectors of this graph.  Default: FP32 for the
  * normalized Laplacian (spectrum in [0, 2]; GPU and FP64 results agree to
  * ~1e-5 relative), FP64 for the combinatorial one, whose spectrum spans

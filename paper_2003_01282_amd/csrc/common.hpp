@@ -77,6 +77,11 @@ struct BuildPartial {
     long long pad;
 };
 
+// Bytes of the last-level (Infinity) cache the automatic hot window fills with
+// the hottest probe rows (of 256 MB; the rest holds tails, indices and the
+// streamed vectors).
+constexpr size_t kCacheBudget = (size_t)200 << 20;
+
 // Grid of the self-loop pass of the build (one FP64 partial per block).
 constexpr int kLoopBlocks = 4096;
 
@@ -142,6 +147,7 @@ struct slaq_graph_s {
     int heavy_min;
     int piece;
     int tile_quads;          // probe tile of the gather kernels in 16-byte words (0 = automatic)
+    int64_t cache_rows;      // hot window of the gathers, rows per column range (-1 = automatic)
     int precision;           // SLAQ_PREC_* of the Lanczos vectors
     hipStream_t stream;      // stream of the build (slaq_graph_info waits on it)
 };

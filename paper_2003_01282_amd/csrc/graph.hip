@@ -630,6 +630,7 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->heavy_min = small ? kSmallHeavyMin : kDefaultHeavyMin;
     g->piece = small ? kSmallPiece : kDefaultPiece;
     g->tile_quads = 0;
+    g->cache_rows = -1;
     g->precision = laplacian == SLAQ_LAP_COMBINATORIAL ? SLAQ_PREC_FP64 : SLAQ_PREC_FP32;
     g->n = n;
     g->nnz = nnz;
@@ -719,6 +720,21 @@ slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads) {
     SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
     SLAQ_REQUIRE(tile_quads >= 0 && tile_quads <= 64, SLAQ_ERR_INVALID_ARG, "tile_quads must be in [0, 64]");
     g->tile_quads = tile_quads;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_set_cache_rows(slaq_graph_t g, int64_t rows) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    SLAQ_REQUIRE(rows >= -1, SLAQ_ERR_INVALID_ARG, "rows must be >= -1 (-1 = automatic)");
+    g->cache_rows = rows;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_cache_rows(slaq_graph_t g, int64_t* rows) {
+    clear_error();
+    SLAQ_REQUIRE(g && rows, SLAQ_ERR_INVALID_ARG, "graph or rows is NULL");
+    *rows = g->cache_rows;
     return SLAQ_OK;
 }
 

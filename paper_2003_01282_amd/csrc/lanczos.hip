@@ -132,6 +132,69 @@ __device__ __forceinline__ Quad<V> qload(const V* p, int q) {
     return r;
 }
 
+// Gathers and the Infinity Cache.  On a relabelled graph the labels of each
+// column range run in decreasing degree order, so the range's first rows are
+// the ones every step gathers most.  Gathers of those rows are ordinary loads;
+// gathers of the rest, and the once-read column indices and piece partials,
+// carry the non-temporal hint, which keeps their lines from displacing the hot
+// rows in the 256 MB last-level cache (measured at R-MAT 26: piece kernel
+// 99.4 -> 92 ms; hinting every gather instead: 131 ms).  A gathered column
+// travels between lanes with the hint folded into its sign bit (labels are
+// below 2^31).
+__device__ __forceinline__ Quad<float> qload_nt(const Quad<float>* p) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 v = __builtin_nontemporal_load((const f4*)p);
+    Quad<float> q;
+    q.v[0] = v.x;
+    q.v[1] = v.y;
+    q.v[2] = v.z;
+    q.v[3] = v.w;
+    return q;
+}
+__device__ __forceinline__ Quad<double> qload_nt(const Quad<double>* p) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_nontemporal_load((const d2*)p);
+    Quad<double> q;
+    q.v[0] = v.x;
+    q.v[1] = v.y;
+    return q;
+}
+
+// a packed column: the label, negative when its gather is a cold one
+__device__ __forceinline__ int32_t pack_col(int32_t c, bool hot) { return hot ? c : (int32_t)((uint32_t)c | 0x80000000u); }
+
+// row `c` of the lane's quad column (stride ms), hint from the packed column
+template <typename V>
+__device__ __forceinline__ Quad<V> gather(const Quad<V>* __restrict__ Rl, int32_t packed, int ms) {
+    const Quad<V>* p = Rl + (int64_t)(packed & 0x7fffffff) * ms;
+    return packed >= 0 ? *p : qload_nt(p);
+}
+
+// The column ranges' first labels (device, from the build) and the hot
+// window (rows per range whose gathers stay cached); a window of at least n
+// rows caches every gather.
+struct CacheWindow {
+    const int64_t* bounds;
+    int64_t hot;
+};
+
+// the range starts in registers, for kernels whose gathers span all ranges
+struct HotRanges {
+    int64_t lo[kColRanges];
+    int64_t hot;
+    __device__ __forceinline__ explicit HotRanges(const CacheWindow& cw) : hot(cw.hot) {
+#pragma unroll
+        for (int x = 0; x < kColRanges; ++x) lo[x] = cw.bounds[x];
+    }
+    // label offset of column c within its range is below the window
+    __device__ __forceinline__ bool hot_col(int64_t c) const {
+        int64_t l = lo[0];
+#pragma unroll
+        for (int x = 1; x < kColRanges; ++x) l = c >= lo[x] ? lo[x] : l;
+        return c - l < hot;
+    }
+};
+
 template <typename V>
 __device__ __forceinline__ Quad<V> qshfl(const Quad<V>& a, int src) {
     Quad<V> r;
@@ -236,13 +299,14 @@ template <int MODE, bool WEIGHTED, typename V>
 __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t k1, int gbase, int gl, int G,
                                               const int32_t* __restrict__ col, const float* __restrict__ w,
                                               const V* __restrict__ diag, const Quad<V>* __restrict__ Rl,
-                                              int ms, bool lane_ok) {
+                                              int ms, bool lane_ok, const HotRanges& hr) {
     for (int64_t kb = k0; kb < k1; kb += G) {
         const int cnt = (int)((k1 - kb) < G ? (k1 - kb) : G);
         int32_t cl = 0;
         V sl = V(0);
         if (gl < cnt) {
-            cl = col[kb + gl];
+            const int32_t c = __builtin_nontemporal_load(col + kb + gl);
+            cl = pack_col(c, hr.hot_col(c));
             sl = WEIGHTED ? (V)w[kb + gl] : V(1);
         }
         int u = 0;
@@ -256,14 +320,14 @@ __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t 
                 s[v] = __shfl(sl, gbase + u + v);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? Rl[(int64_t)c[v] * ms] : qzero<V>();
+            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? gather(Rl, c[v], ms) : qzero<V>();
 #pragma unroll
             for (int v = 0; v < 4; ++v) qfma(s[v], x[v], acc);
         }
         for (; u < cnt; ++u) {
             const int32_t c = __shfl(cl, gbase + u);
             const V s = __shfl(sl, gbase + u);
-            if (lane_ok) qfma(s, Rl[(int64_t)c * ms], acc);
+            if (lane_ok) qfma(s, gather(Rl, c, ms), acc);
         }
     }
 }
@@ -282,7 +346,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                                                    const V* __restrict__ diag,
                                                    const Quad<V>* __restrict__ R,
                                                    Quad<V>* __restrict__ P, int F, VecMap vm, int G, int K, int piece,
-                                                   int tile0, int TQ) {
+                                                   int tile0, int TQ, CacheWindow cw) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int tile = tile0 + (int)blockIdx.y;
@@ -296,6 +360,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
     vm.lane(quad, mo, ms);
     const Quad<V>* __restrict__ Rl = R + mo;
     const int x = blockIdx.x % kColRanges;
+    const int64_t rlo = cw.bounds[x];
     const int64_t waves_x = (int64_t)(gridDim.x / kColRanges) * 4;
     const int64_t wi = (int64_t)(blockIdx.x / kColRanges) * 4 + wave;
     const int64_t* so = segoff + (int64_t)x * cap;
@@ -326,7 +391,8 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
             int32_t cl = 0;
             V sl = V(0);
             if (lane < cnt) {
-                cl = col[kb + lane];
+                const int32_t c = __builtin_nontemporal_load(col + kb + lane);
+                cl = pack_col(c, (int64_t)c - rlo < cw.hot);
                 sl = WEIGHTED ? (V)w[kb + lane] : V(1);
             }
             const int rounds = (cnt + K - 1) / K;
@@ -345,7 +411,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                 }
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v)
-                    xv[v] = (lane_ok && s[v] != V(0)) ? Rl[(int64_t)c[v] * ms] : qzero<V>();
+                    xv[v] = (lane_ok && s[v] != V(0)) ? gather(Rl, c[v], ms) : qzero<V>();
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v) qfma(s[v], xv[v], acc);
             }
@@ -354,7 +420,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                 const int src = u < 64 ? u : 63;
                 const int32_t c = __shfl(cl, src);
                 const V s = __shfl(sl, src);
-                if (lane_ok && u < cnt) qfma(s, Rl[(int64_t)c * ms], acc);
+                if (lane_ok && u < cnt) qfma(s, gather(Rl, c, ms), acc);
             }
         }
         // fixed-order tree over the K groups (lane + st*G)
@@ -448,12 +514,12 @@ __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__
             for (; p + 3 * K < p1; p += 4 * K) {
                 Quad<V> xv[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) xv[v] = lane_ok ? P[(p + v * K) * F + quad] : qzero<V>();
+                for (int v = 0; v < 4; ++v) xv[v] = lane_ok ? qload_nt(&P[(p + v * K) * F + quad]) : qzero<V>();
 #pragma unroll
                 for (int v = 0; v < 4; ++v) qadd(acc, xv[v]);
             }
             for (; p < p1; p += K)
-                if (lane_ok) qadd(acc, P[p * F + quad]);
+                if (lane_ok) qadd(acc, qload_nt(&P[p * F + quad]));
             idx += p1 - p0;
         }
         for (int sd = 1; sd < K; sd <<= 1) {
@@ -480,11 +546,12 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
                                                  const Quad<V>* __restrict__ Rp,
                                                  Quad<V>* __restrict__ W, const V* __restrict__ coef,
                                                  int has_prev, double* __restrict__ part, int nb, int F, VecMap vm,
-                                                 int G, int K, int ld, int rw, int tile0, int TQ) {
+                                                 int G, int K, int ld, int rw, int tile0, int TQ, CacheWindow cw) {
     constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int gbase = gi * G;
+    const HotRanges hr(cw);
     const int tile = tile0 + (int)blockIdx.y;
     const int quad = tile * TQ + gl;
     const bool in_group = gi < K;
@@ -518,7 +585,7 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
             if (!in_group || t >= rw || i >= n || e == s) continue;  // isolated: nothing stored
             if (e - s >= heavy_min) continue;  // heavy rows: spmm_heavy
             Quad<V> acc = qzero<V>();
-            group_segment<MODE, WEIGHTED, V>(acc, s, e, gbase, gl, G, col, w, diag, R + mo, ms, lane_ok);
+            group_segment<MODE, WEIGHTED, V>(acc, s, e, gbase, gl, G, col, w, diag, R + mo, ms, lane_ok, hr);
             if (!lane_ok) continue;
             row_epilogue<MODE, V>(i, acc, diag, R, Rp, W, sg, tp, has_prev, mo, ms, s1);
         }
@@ -760,6 +827,17 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     return L;
 }
 
+// The hot window: rows per column range whose gathers keep their lines
+// cached.  Only a relabelled graph has its hot rows at the front of each
+// range; elsewhere every gather is cached.  Automatic: the window whose probe
+// rows (F quads each, all ranges) fill kCacheBudget of the last-level cache.
+static CacheWindow cache_window(const slaq_graph_s* g, int F) {
+    CacheWindow cw{g->bounds, INT64_MAX / 2};
+    if (!g->relabeled) return cw;
+    cw.hot = g->cache_rows >= 0 ? g->cache_rows : (int64_t)(kCacheBudget / ((size_t)kColRanges * 16 * F));
+    return cw;
+}
+
 static int sweep_grid(int64_t n, int F, int* rows_per_sweep) {
     int64_t rows = n;
     const int64_t max_threads = 256LL * 8192;
@@ -805,6 +883,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
     unsigned* const dstat = device_status_word();
     SLAQ_REQUIRE(dstat, SLAQ_ERR_HIP, "device status word unavailable");
 
+    const CacheWindow cw = cache_window(g, L.F);
     const double sigma1 = 1.0 / sqrt((double)g->n);
     hipLaunchKernelGGL(state_init<V>, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef,
                        g->stats);
@@ -826,13 +905,13 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
                 SLAQ_TIMED("spmm_pieces", st,
                            SLAQ_DISPATCH(mode, weighted, spmm_pieces, dim3(L.piece_blocks, 1), dim3(256), 0, st,
                                          g->stats, g->segk, g->segoff, cap, g->col_idx, g->weights, diag, Rb[cur], P,
-                                         L.F, L.vm, L.G, L.K, g->piece, tile, L.TQ));
+                                         L.F, L.vm, L.G, L.K, g->piece, tile, L.TQ, cw));
                 SLAQ_LAUNCHED();
             }
             SLAQ_TIMED("spmm_rows", st,
                        SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st, g->stats,
                                      g->row_ptr, g->col_idx, g->weights, diag, g->heavy_min, Rb[cur], Rb[prev],
-                                     Rb[wbuf], coef, hp, part1, nbp, L.F, L.vm, L.G, L.K, L.ld, L.rw, tile, L.TQ));
+                                     Rb[wbuf], coef, hp, part1, nbp, L.F, L.vm, L.G, L.K, L.ld, L.rw, tile, L.TQ, cw));
             SLAQ_LAUNCHED();
             {  // always launched: its blocks write their (zero) dot partials even without heavy rows
                 SLAQ_TIMED("spmm_heavy", st, {

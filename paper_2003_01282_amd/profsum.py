@@ -70,10 +70,14 @@ def calls(d, stem, out=sys.stdout):
 
 
 def pmc_table(d):
-    """{kernel: {counter: [per-dispatch values]}} over every counter file under d."""
+    """{kernel: {counter: [per-dispatch values in dispatch order]}} over every
+    counter file under d."""
     acc = defaultdict(lambda: defaultdict(list))
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-        for r in csv.DictReader(open(f)):
+        rows = list(csv.DictReader(open(f)))
+        if rows and "Dispatch_Id" in rows[0]:
+            rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        for r in rows:
             k = short(r.get("Kernel_Name", r.get("Kernel-Name", "?")))
             acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     return acc
@@ -92,13 +96,24 @@ def _find(table, stem):
     raise KeyError(stem)
 
 
+def calibration_dispatch(values, copy_bytes):
+    """The counter value (KiB) of the calibration copy among the run's copy
+    dispatches in dispatch order: the first one that reads between 0.4 and 1.1
+    times the copy's known size (bench.py makes that copy before anything
+    else it copies)."""
+    for v in values:
+        if 0.4 <= v * 1024.0 / copy_bytes <= 1.1:
+            return v
+    raise SystemExit(f"no calibration copy of {copy_bytes} bytes among {len(values)} copy dispatches")
+
+
 def traffic(fetch_dir, write_dir, copy_bytes, out_json):
     rec = {"kernels": {}, "digest": kernel_sources_digest()}
     per_launch = 0.0
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         t = pmc_table(d)
-        copy = _find(t, COPY_KERNEL)[counter]
-        scale = copy_bytes / (sum(copy) * 1024.0)  # true bytes per counted byte
+        copy = calibration_dispatch(_find(t, COPY_KERNEL)[counter], copy_bytes)
+        scale = copy_bytes / (copy * 1024.0)  # true bytes per counted byte
         rec[f"{counter}_scale"] = scale
         for k in SPMM_STAGE + (UPDATE_KERNEL,):
             v = _find(t, f"slaq::{k}")[counter]

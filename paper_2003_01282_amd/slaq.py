@@ -55,6 +55,8 @@ SIGNATURES = {
     "slaq_vnge_cv": [_vp, _vp, _vp, _int, _int, _vp, _int, _vp, _vp],
     "slaq_graph_set_schedule": [_vp, _int, _int, _vp],
     "slaq_graph_set_tile": [_vp, _int],
+    "slaq_graph_set_cache_rows": [_vp, _i64],
+    "slaq_graph_cache_rows": [_vp, ctypes.POINTER(_i64)],
     "slaq_graph_set_precision": [_vp, _int],
     "slaq_graph_precision": [_vp, ctypes.POINTER(_int)],
     "slaq_graph_schedule": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
@@ -179,6 +181,14 @@ class Graph:
 
     def set_tile(self, tile_quads):
         _check(lib().slaq_graph_set_tile(self.handle, tile_quads))
+
+    def set_cache_rows(self, rows):
+        _check(lib().slaq_graph_set_cache_rows(self.handle, int(rows)))
+
+    def cache_rows(self):
+        r = _i64()
+        _check(lib().slaq_graph_cache_rows(self.handle, ctypes.byref(r)))
+        return r.value
 
     def set_precision(self, precision):
         _check(lib().slaq_graph_set_precision(self.handle, precision))

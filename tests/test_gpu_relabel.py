@@ -224,3 +224,25 @@ def test_flag_conflict_rejected():
                                   S.SLAQ_FLAG_RELABEL | S.SLAQ_FLAG_NO_RELABEL, S._ptr(dinv), S._ptr(scratch),
                                   scratch.numel(), None, S.ctypes.byref(h))
     assert st == 1  # SLAQ_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("precision", [S.SLAQ_PREC_FP32, S.SLAQ_PREC_FP64])
+def test_cache_window_hints_leave_results_unchanged(precision):
+    # the hot window only chooses load hints: every window gives the same
+    # coefficients bit for bit (hub rows in pieces, light rows, all ranges)
+    print(f"\n[gpu] cache window sweep, precision {precision}", flush=True)
+    csr = inputs.chung_lu(20_000, 150_000, 2.2, seed=3)
+    rp, ci = S.to_device(csr)
+    g = S.build_graph(rp, ci, relabel=True)
+    g.set_precision(precision)
+    assert g.cache_rows() == -1
+    ref = [x.cpu().numpy() for x in S.lanczos(g, 37, 8, 5)]
+    assert g.schedule()["n_heavy"] > 0
+    for rows in (0, 1, 100, 2500, 10**9):
+        g.set_cache_rows(rows)
+        assert g.cache_rows() == rows
+        got = [x.cpu().numpy() for x in S.lanczos(g, 37, 8, 5)]
+        for r, x in zip(ref, got):
+            np.testing.assert_array_equal(x, r)
+    with pytest.raises(S.SlaqError):
+        g.set_cache_rows(-2)

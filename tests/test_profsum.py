@@ -41,8 +41,9 @@ def test_stats_and_calls(tmp_path):
 
 
 def test_traffic_scaling(tmp_path):
-    # the copy of 1 GiB reads as 2 x 262,144 KiB of FETCH_SIZE (the counter
-    # under-reports by 2) and as 1,048,576 KiB of WRITE_SIZE
+    # the copy of 1 GiB reads as 524,288 KiB of FETCH_SIZE (the counter
+    # under-reports by 2) and as 1,048,576 KiB of WRITE_SIZE; the run's later
+    # copies (a few bytes, an 8 GiB array, half a GiB) are not the calibration
     fetch, write = tmp_path / "f", tmp_path / "w"
     fetch.mkdir()
     write.mkdir()
@@ -50,12 +51,14 @@ def test_traffic_scaling(tmp_path):
     kern = ["void slaq::spmm_pieces<0>(a)", "void slaq::spmm_rows<0>(a)", "void slaq::spmm_heavy<0>(a)",
             "slaq::update<float>(a)"]
     write_csv(fetch / "c_counter_collection.csv",
-              [{"Kernel_Name": copy, "Counter_Name": "FETCH_SIZE", "Counter_Value": 262144.0}] * 2 +
+              [{"Kernel_Name": copy, "Counter_Name": "FETCH_SIZE", "Counter_Value": v}
+               for v in (524288.0, 2.5, 8218193.5, 262144.0)] +
               [{"Kernel_Name": k, "Counter_Name": "FETCH_SIZE", "Counter_Value": v}
                for k, v in zip(kern, (1000.0, 500.0, 100.0, 50.0))] +
               [{"Kernel_Name": kern[0], "Counter_Name": "FETCH_SIZE", "Counter_Value": 3000.0}])
     write_csv(write / "c_counter_collection.csv",
-              [{"Kernel_Name": copy, "Counter_Name": "WRITE_SIZE", "Counter_Value": 1048576.0}] +
+              [{"Kernel_Name": copy, "Counter_Name": "WRITE_SIZE", "Counter_Value": v}
+               for v in (1048576.0, 16436201.0, 0.0625, 530053.0)] +
               [{"Kernel_Name": k, "Counter_Name": "WRITE_SIZE", "Counter_Value": v}
                for k, v in zip(kern, (10.0, 20.0, 30.0, 40.0))])
     out_json = tmp_path / "t.json"
@@ -69,3 +72,10 @@ def test_traffic_scaling(tmp_path):
     assert rec["update_bytes_per_launch"] == 50 * 1024 * 2 + 40 * 1024
     assert rec["digest"] == P.kernel_sources_digest()
 
+
+
+def test_traffic_calibration_is_the_first_copy_of_its_size():
+    import pytest
+    assert P.calibration_dispatch([3.0, 524288.0, 8e6, 530000.0], float(1 << 30)) == 524288.0
+    with pytest.raises(SystemExit):
+        P.calibration_dispatch([8e6, 2.0], float(1 << 30))
