@@ -159,6 +159,20 @@ slaq_status slaq_graph_set_tile(slaq_graph_t g, int tile_quads);
 slaq_status slaq_graph_set_cache_rows(slaq_graph_t g, int64_t rows);
 slaq_status slaq_graph_cache_rows(slaq_graph_t g, int64_t* rows);
 
+/* Single-launch Lanczos (the recurrence of §3.1 with its m steps in one
+ * kernel): one workgroup per CU at most, two device-wide barriers per step,
+ * the per-probe sums formed in workgroup order by every workgroup.  For
+ * graphs too small to fill the chip, where six launches per step cost more
+ * than the work.  blocks: -1 (default) = automatic, used below 2^18 stored
+ * entries with one workgroup per 80 rows (8 to 128); 0 = never; 1..256 =
+ * that many workgroups (capped at the CU count and at what stays resident).  Applies to graphs kept in caller order with
+ * at most 16 quads per probe row (nv <= 64 in FP32, 32 in FP64); otherwise,
+ * and for any other setting, the stage kernels run.  The workgroups wait for
+ * each other: they must all be resident at once, so no other work should
+ * hold the device's CUs during the call (a wait that runs out sets
+ * SLAQ_STATUS_GRID). */
+slaq_status slaq_graph_set_fused(slaq_graph_t g, int blocks);
+
 /* Precision of the Lanczos vectors of this graph.  Default: FP32 for the
  * normalized Laplacian (spectrum in [0, 2]; GPU and FP64 results agree to
  * ~1e-5 relative), FP64 for the combinatorial one, whose spectrum spans
@@ -457,8 +471,11 @@ slaq_status slaq_profile_read(const char* kernel, int64_t* launches, double* tot
  * written).  Every kernel also ORs its bits into one status word per device:
  * slaq_device_status waits for `stream`, returns the word in *bits (may be
  * NULL), clears it when clear != 0, and returns SLAQ_ERR_NUMERIC when it was
- * non-zero.  Work on other streams of the device is not waited for. */
-enum { SLAQ_STATUS_NONFINITE = 1u, SLAQ_STATUS_NO_CONVERGENCE = 2u };
+ * non-zero.  Work on other streams of the device is not waited for.
+ * SLAQ_STATUS_GRID: a single-launch Lanczos run (slaq_graph_set_fused) found
+ * its workgroups not all resident at once and stopped early; its outputs are
+ * incomplete. */
+enum { SLAQ_STATUS_NONFINITE = 1u, SLAQ_STATUS_NO_CONVERGENCE = 2u, SLAQ_STATUS_GRID = 4u };
 slaq_status slaq_device_status(unsigned* bits, int clear, void* stream);
 
 /* Thread-local description of the last non-OK status ("" if none). */

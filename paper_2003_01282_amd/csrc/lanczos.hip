@@ -729,12 +729,405 @@ __global__ void __launch_bounds__(256) finalize_b(const double* __restrict__ par
     ps[p] = s;
 }
 
+// ------------------------------------------------ single-launch path ------
+// A graph too small to fill the chip runs the whole recurrence in one launch
+// of at most one workgroup per CU instead of six launches per step: per step
+//   A  heavy rows (degree >= heavy_min), one workgroup each (its 4K lane
+//      groups split the row's nonzeros, fixed-order sums over groups, then
+//      waves), then light rows in windows of rw rows per wave; the row
+//      epilogue of spmm_rows; FP64 partials of R_j . w per workgroup
+//   -- grid barrier --
+//   B  every workgroup sums the partials in workgroup order and forms alpha_j
+//      (the finalize_a arithmetic, the same in every workgroup, so the
+//      per-probe state needs no broadcast); R_{j+1} = w - a_j R_j on its rows,
+//      partials of ||R_{j+1}||^2
+//   -- grid barrier --
+//   C  beta_j, breakdown, sigma_{j+1}, tau_j as in finalize_b
+// Workgroup 0 alone writes alpha, beta and the step counts.  The barrier is a
+// device-wide arrival counter (zeroed by fused_reset before the launch) with
+// release/acquire fences; its wait is bounded, so a grid whose workgroups are
+// not all resident at once ends with SLAQ_STATUS_GRID set instead of hanging
+// (the grid is sized to what the occupancy query says stays resident).
+constexpr int kFusedMaxBlocks = 256;
+constexpr int kFusedMaxQuads = 16;  // F <= 16: nv <= 64 (FP32) or 32 (FP64)
+constexpr unsigned kSpinLimit = 1u << 20;
+
+template <typename V>
+struct FusedArgs {
+    GraphStats* st;
+    const int64_t* rp;
+    const int32_t* col;
+    const float* w;
+    const V* diag;
+    const int32_t* perm;
+    const int32_t* hrow;
+    int heavy_min;
+    Quad<V>* R0;
+    Quad<V>* R1;
+    Quad<V>* R2;
+    int F, G, K, ld, nv, m, rw;
+    VecMap vm;
+    uint64_t seed;
+    double sigma1, eps_bd;
+    double* alpha;
+    double* beta;
+    int32_t* steps;
+    double* part;  // [2][ld][kFusedMaxBlocks]
+    unsigned* bar;
+    unsigned* dstat;
+    CacheWindow cw;
+};
+
+// Barrier counters, each on a 128-byte line of its own: [0] the rounds the
+// eight groups (workgroups b with b mod 8 = x, one XCD each) have completed,
+// [1 + x] group x's arrivals.
+constexpr int kBarStride = 32;  // unsigned words per counter line
+constexpr size_t kBarBytes = (size_t)(1 + kColRanges) * kBarStride * sizeof(unsigned);
+
+__global__ void fused_reset(unsigned* bar) {
+    if (threadIdx.x <= kColRanges) bar[threadIdx.x * kBarStride] = 0u;
+}
+
+// Every workgroup has arrived `round` times; false if the wait ran out.  Two
+// levels: a workgroup counts itself in its group's counter, the group's last
+// arrival of the round counts the group in counter 0, and every workgroup
+// waits for counter 0 to reach round x groups (256 arrivals on one address
+// would serialize: ~6.6 us per barrier at 128 workgroups).
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned round, int* s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned nb = gridDim.x;
+        const unsigned x = blockIdx.x % kColRanges;
+        const unsigned members = (nb - x + kColRanges - 1) / kColRanges;
+        const unsigned groups = nb < (unsigned)kColRanges ? nb : (unsigned)kColRanges;
+        // release: this workgroup's writes (L2 written back) before its arrival
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned old =
+            __hip_atomic_fetch_add(bar + (1 + x) * kBarStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == round * members) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // the wait polls with plain coherent loads; one acquire after it
+        // (an acquiring poll would invalidate the L2 at every iteration)
+        const unsigned target = round * groups;
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                ok = 0;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// Fixed-order sum over the workgroups' partials part[p][0..nb) of every
+// probe p < ld into out[p] (chunks of workgroups summed by all threads, then
+// the chunks in order by thread p).  Ends with a barrier.
+__device__ __forceinline__ void sum_workgroup_partials(const double* __restrict__ part, int nb, int ld,
+                                                       double* red, double* out) {
+    const int t = threadIdx.x;
+    int C = 256 / ld;
+    if (C > 8) C = 8;
+    if (C < 1) C = 1;
+    if (t < C * ld) {
+        const int p = t % ld, c = t / ld;
+        double a = 0.0;
+        for (int b = c; b < nb; b += C) a += __hip_atomic_load(part + (int64_t)p * kFusedMaxBlocks + b,
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        red[c * ld + p] = a;
+    }
+    __syncthreads();
+    if (t < ld) {
+        double a = 0.0;
+        for (int c = 0; c < C; ++c) a += red[c * ld + t];
+        out[t] = a;
+    }
+    __syncthreads();
+}
+
+template <int MODE, bool WEIGHTED, typename V>
+__global__ void __launch_bounds__(256) lanczos_fused(FusedArgs<V> a) {
+    constexpr int E = Quad<V>::E;
+    __shared__ ProbeState sps[4 * kFusedMaxQuads];
+    __shared__ V scoef[3 * 4 * kFusedMaxQuads];
+    __shared__ double sred[256];
+    __shared__ double ssum[4 * kFusedMaxQuads];
+    __shared__ Quad<V> hacc[4][64];
+    __shared__ int s_ok;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int G = a.G, K = a.K, F = a.F, ld = a.ld;
+    const int gi = lane / G, gl = lane % G, gbase = gi * G;
+    const bool in_group = gi < K;
+    const int quad = gl;
+    const bool lane_ok = in_group && quad < F;
+    int64_t mo;
+    int ms;
+    a.vm.lane(quad, mo, ms);
+    const HotRanges hr(a.cw);
+    const int nb = gridDim.x;
+    const bool lead = blockIdx.x == 0;
+    GraphStats* st = a.st;
+    const int64_t n = st->n_rows;
+    const int64_t nh = st->n_heavy;
+    const double n_iso = (double)st->n_isolated;
+    const double bound = MODE == SLAQ_LAP_NORMALIZED ? 2.0 : 2.0 * st->max_degree;
+    const V* __restrict__ diag = a.diag;
+    double* part1 = a.part;
+    double* part2 = a.part + (int64_t)ld * kFusedMaxBlocks;
+    unsigned round = 0;
+
+    // ---- per-probe state (every workgroup the same) and X_1 ----------------
+    for (int p = threadIdx.x; p < ld; p += blockDim.x) {
+        const bool on = p < a.nv;
+        ProbeState z;
+        z.sigma = on ? a.sigma1 : 0.0;
+        z.tau = 0.0;
+        z.rho = 1.0;
+        z.rho_prev = 0.0;
+        z.a = 0.0;
+        z.active = on ? 1 : 0;
+        z.pad = 0;
+        sps[p] = z;
+        scoef[p] = on ? (V)a.sigma1 : V(0);
+        scoef[ld + p] = V(0);
+        scoef[2 * ld + p] = V(0);
+    }
+    if (lead) {
+        if (threadIdx.x == 0) st->status = 0u;
+        for (int k = threadIdx.x; k < a.nv * a.m; k += blockDim.x) {
+            a.alpha[k] = 0.0;
+            a.beta[k] = 0.0;
+        }
+        for (int p = threadIdx.x; p < a.nv; p += blockDim.x) a.steps[p] = a.m;
+    }
+    {
+        const int64_t total = n * F;
+        for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)nb * blockDim.x) {
+            const int64_t i = x / F;
+            const int q = (int)(x % F);
+            if (diag[i] == V(0)) continue;
+            int64_t o;
+            int sd;
+            a.vm.lane(q, o, sd);
+            const uint64_t id = a.perm ? (uint64_t)a.perm[i] : (uint64_t)i;
+            const int p0 = E * q;
+            const uint64_t z = splitmix64(a.seed, 64ull * id + (uint64_t)(p0 >> 6));
+            const V one = MODE == SLAQ_LAP_NORMALIZED ? diag[i] : V(1);
+            Quad<V> v;
+#pragma unroll
+            for (int c = 0; c < E; ++c) {
+                const V sgn = ((z >> ((p0 & 63) + c)) & 1ull) ? -one : one;
+                v.v[c] = (p0 + c < a.nv) ? sgn : V(0);
+            }
+            a.R0[o + i * sd] = v;
+        }
+    }
+    if (!grid_barrier(a.bar, ++round, &s_ok)) {
+        if (threadIdx.x == 0) raise_status(a.dstat, SLAQ_STATUS_GRID);
+        return;
+    }
+
+    Quad<V>* Rc = a.R0;
+    Quad<V>* Rp = a.R1;
+    Quad<V>* W = a.R2;
+    const int64_t nwin = (n + a.rw - 1) / a.rw;
+    const int rounds = (a.rw + K - 1) / K;
+    const int64_t nwaves = (int64_t)nb * 4;
+    for (int j = 1; j <= a.m; ++j) {
+        const int hp = j > 1 ? 1 : 0;
+        Quad<V> sg = qzero<V>(), tp = qzero<V>();
+        if (lane_ok) {
+            sg = qload(scoef, quad);
+            if (hp) tp = qload(scoef + ld, quad);
+        }
+        double s1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) s1[e] = 0.0;
+        // -- A: heavy rows.  The longest (>= 8 nonzeros per lane group of the
+        // workgroup) take a whole workgroup each: its 4K groups split the row,
+        // fixed-order sums over groups, then over waves through LDS.  The
+        // others take one wave each: its K groups split the row, fixed-order
+        // sums over the groups by lane shuffles.
+        const int64_t big = 32 * (int64_t)K;
+        for (int64_t h = blockIdx.x; h < nh; h += nb) {
+            const int64_t i = a.hrow[h];
+            const int64_t rs = a.rp[i], re = a.rp[i + 1];
+            if (re - rs < big) continue;  // workgroup-uniform
+            const int64_t ng = 4 * (int64_t)K;
+            const int64_t chunk = (re - rs + ng - 1) / ng;
+            int64_t k0 = re, k1 = re;
+            if (in_group) {
+                const int64_t gg = (int64_t)wave * K + gi;
+                k0 = rs + gg * chunk < re ? rs + gg * chunk : re;
+                k1 = k0 + chunk < re ? k0 + chunk : re;
+            }
+            Quad<V> acc = qzero<V>();
+            group_segment<MODE, WEIGHTED, V>(acc, k0, k1, gbase, gl, G, a.col, a.w, diag, Rc + mo, ms, lane_ok, hr);
+            for (int sd = 1; sd < K; sd <<= 1) {
+                const int src = lane + sd * G < 64 ? lane + sd * G : lane;
+                const Quad<V> o = qshfl(acc, src);
+                if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) qadd(acc, o);
+            }
+            if (gi == 0) hacc[wave][lane] = acc;
+            __syncthreads();
+            if (wave == 0 && gi == 0 && lane_ok) {
+                Quad<V> r = hacc[0][lane];
+                qadd(r, hacc[1][lane]);
+                qadd(r, hacc[2][lane]);
+                qadd(r, hacc[3][lane]);
+                row_epilogue<MODE, V>(i, r, diag, Rc, Rp, W, sg, tp, hp, mo, ms, s1);
+            }
+            __syncthreads();
+        }
+        for (int64_t h = (int64_t)blockIdx.x * 4 + wave; h < nh; h += nwaves) {
+            const int64_t i = a.hrow[h];
+            const int64_t rs = a.rp[i], re = a.rp[i + 1];
+            if (re - rs >= big) continue;  // wave-uniform
+            const int64_t chunk = (re - rs + K - 1) / K;
+            int64_t k0 = re, k1 = re;
+            if (in_group) {
+                k0 = rs + gi * chunk < re ? rs + gi * chunk : re;
+                k1 = k0 + chunk < re ? k0 + chunk : re;
+            }
+            Quad<V> acc = qzero<V>();
+            group_segment<MODE, WEIGHTED, V>(acc, k0, k1, gbase, gl, G, a.col, a.w, diag, Rc + mo, ms, lane_ok, hr);
+            for (int sd = 1; sd < K; sd <<= 1) {
+                const int src = lane + sd * G < 64 ? lane + sd * G : lane;
+                const Quad<V> o = qshfl(acc, src);
+                if (in_group && (gi % (2 * sd)) == 0 && gi + sd < K) qadd(acc, o);
+            }
+            if (gi == 0 && lane_ok) row_epilogue<MODE, V>(i, acc, diag, Rc, Rp, W, sg, tp, hp, mo, ms, s1);
+        }
+        // -- A: light rows, a lane group per row, windows of rw rows per wave
+        for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += nwaves) {
+            const int64_t r0 = win * a.rw;
+            const int64_t ia = r0 + lane < n ? r0 + lane : n;
+            const int64_t ib = r0 + lane + 1 < n ? r0 + lane + 1 : n;
+            const int64_t rs_l = a.rp[ia], re_l = a.rp[ib];
+            for (int rr = 0; rr < rounds; ++rr) {
+                const int t = rr * K + gi;
+                const int src = t < 64 ? t : 63;
+                const int64_t rs = __shfl(rs_l, src), re = __shfl(re_l, src);
+                const int64_t i = r0 + t;
+                if (!in_group || t >= a.rw || i >= n || re == rs) continue;
+                if (re - rs >= a.heavy_min) continue;
+                Quad<V> acc = qzero<V>();
+                group_segment<MODE, WEIGHTED, V>(acc, rs, re, gbase, gl, G, a.col, a.w, diag, Rc + mo, ms, lane_ok,
+                                                 hr);
+                if (!lane_ok) continue;
+                row_epilogue<MODE, V>(i, acc, diag, Rc, Rp, W, sg, tp, hp, mo, ms, s1);
+            }
+        }
+        block_reduce_store<E>(s1, part1, kFusedMaxBlocks, F, G, K, ld, 0, F);
+        if (!grid_barrier(a.bar, ++round, &s_ok)) {
+            if (threadIdx.x == 0) raise_status(a.dstat, SLAQ_STATUS_GRID);
+            return;
+        }
+        // -- B: alpha_j (finalize_a in every workgroup)
+        sum_workgroup_partials(part1, nb, ld, sred, ssum);
+        if (threadIdx.x < ld) {
+            const int p = threadIdx.x;
+            ProbeState z = sps[p];
+            if (z.active) {
+                const double iso = n_iso * z.rho * (-z.tau * z.rho_prev);
+                const double al = z.sigma * (ssum[p] + iso);
+                if (lead) {
+                    check_finite(al, st, a.dstat);
+                    a.alpha[(int64_t)p * a.m + (j - 1)] = al;
+                }
+                z.a = al * z.sigma;
+                sps[p] = z;
+                scoef[2 * ld + p] = (V)z.a;
+            } else {
+                scoef[2 * ld + p] = V(0);
+            }
+        }
+        __syncthreads();
+        // -- B: R_{j+1} = w - a_j R_j (into R_{j-1}'s block), ||R_{j+1}||^2 partials
+        Quad<V> av = qzero<V>();
+        if (lane_ok) av = qload(scoef + 2 * ld, quad);
+        double s2[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) s2[e] = 0.0;
+        for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += nwaves) {
+            const int64_t r0 = win * a.rw;
+            const V d_l = r0 + lane < n ? diag[r0 + lane] : V(0);
+            for (int rr = 0; rr < rounds; ++rr) {
+                const int t = rr * K + gi;
+                const V d = __shfl(d_l, t < 64 ? t : 63);
+                const int64_t i = r0 + t;
+                if (!lane_ok || t >= a.rw || i >= n || d == V(0)) continue;
+                const int64_t at = mo + i * ms;
+                const Quad<V> wv = W[at];
+                const Quad<V> rv = Rc[at];
+                Quad<V> r;
+#pragma unroll
+                for (int e = 0; e < E; ++e) r.v[e] = vfma(-av.v[e], rv.v[e], wv.v[e]);
+                if (j < a.m) Rp[at] = r;
+                const double wgt = MODE == SLAQ_LAP_NORMALIZED ? 1.0 / ((double)d * (double)d) : 1.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) s2[e] = fma((double)r.v[e] * (double)r.v[e], wgt, s2[e]);
+            }
+        }
+        block_reduce_store<E>(s2, part2, kFusedMaxBlocks, F, G, K, ld, 0, F);
+        if (!grid_barrier(a.bar, ++round, &s_ok)) {
+            if (threadIdx.x == 0) raise_status(a.dstat, SLAQ_STATUS_GRID);
+            return;
+        }
+        // -- C: beta_j, breakdown, next sigma and tau (finalize_b in every workgroup)
+        sum_workgroup_partials(part2, nb, ld, sred, ssum);
+        if (threadIdx.x < ld) {
+            const int p = threadIdx.x;
+            ProbeState z = sps[p];
+            if (z.active) {
+                const double rho_next = -z.tau * z.rho_prev - z.a * z.rho;
+                const double nrm2 = ssum[p] + n_iso * rho_next * rho_next;
+                const double be = sqrt(fmax(nrm2, 0.0));
+                if (lead) {
+                    check_finite(nrm2, st, a.dstat);
+                    a.beta[(int64_t)p * a.m + (j - 1)] = be;
+                }
+                if (j < a.m && !(be > a.eps_bd * bound)) {
+                    if (lead) a.steps[p] = j;
+                    z.active = 0;
+                    z.sigma = 0.0;
+                    z.tau = 0.0;
+                    scoef[p] = V(0);
+                    scoef[ld + p] = V(0);
+                    scoef[2 * ld + p] = V(0);
+                } else {
+                    z.tau = be * z.sigma;
+                    z.sigma = 1.0 / be;
+                    z.rho_prev = z.rho;
+                    z.rho = rho_next;
+                    scoef[p] = (V)z.sigma;
+                    scoef[ld + p] = (V)z.tau;
+                }
+                sps[p] = z;
+            }
+        }
+        __syncthreads();
+        if (j < a.m) {
+            Quad<V>* tq = Rc;
+            Rc = Rp;
+            Rp = tq;
+        }
+    }
+}
+
 // ------------------------------------------------------------ layout ------
 struct Layout {
     int ld, F, G, K, ntiles, TQ, Gu, Ku, ntiles_u, nb_rows, nb_upd, piece_blocks, rw, nb_heavy;
     VecMap vm;
     int64_t max_pieces;
-    size_t off_r[3], off_p, off_part1, off_part2, off_ps, off_coef, total;
+    size_t off_r[3], off_p, off_part1, off_part2, off_ps, off_coef, off_fused, off_bar, total;
 };
 
 constexpr int kRowBlocks = 2048;  // upper bound; the grid is sized to what stays resident
@@ -823,6 +1216,12 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     off += align_up((size_t)L.ld * sizeof(ProbeState), 256);
     L.off_coef = off;
     off += align_up((size_t)3 * L.ld * sizeof(V), 256);
+    // single-launch path: FP64 partials [2][ld][kFusedMaxBlocks] and the
+    // barrier's arrival counter
+    L.off_fused = off;
+    off += align_up((size_t)2 * L.ld * kFusedMaxBlocks * sizeof(double), 256);
+    L.off_bar = off;
+    off += align_up(kBarBytes, 256);
     L.total = off;
     return L;
 }
@@ -836,6 +1235,35 @@ static CacheWindow cache_window(const slaq_graph_s* g, int F) {
     if (!g->relabeled) return cw;
     cw.hot = g->cache_rows >= 0 ? g->cache_rows : (int64_t)(kCacheBudget / ((size_t)kColRanges * 16 * F));
     return cw;
+}
+
+// Workgroups of the single-launch path for this graph and probe count, or 0
+// for the multi-kernel path.  Eligible: caller order (no relabelling), at most
+// kFusedMaxQuads quads per row; automatic (fused = -1) below kFusedAutoNnz
+// stored entries, with one workgroup per 80 rows between 8 and 128 (measured
+// on Chung-Lu n = 10^4, nv = 10, m = 15: 8 / 32 / 128 / 256 workgroups take
+// 3.55 / 1.11 / 0.67 / 0.77 ms; a 100-node path 0.15 ms at 8, where the stage
+// kernels need ~90 launches).  At most one workgroup per CU
+// and never more than stay resident at once.
+constexpr int64_t kFusedAutoNnz = (int64_t)1 << 18;
+
+template <typename V>
+static int fused_blocks(const slaq_graph_s* g, const Layout& L) {
+    if (g->fused == 0 || g->relabeled || L.F > kFusedMaxQuads || L.ntiles != 1) return 0;
+    if (g->fused < 0 && g->nnz >= kFusedAutoNnz) return 0;
+    static const int cap_res = resident_blocks(lanczos_fused<SLAQ_LAP_COMBINATORIAL, true, V>, 256);
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 0;
+    int cap = cus < cap_res ? cus : cap_res;
+    if (cap > kFusedMaxBlocks) cap = kFusedMaxBlocks;
+    int64_t want = g->fused;
+    if (want < 0) {
+        want = (g->n + 79) / 80;
+        want = want < 8 ? 8 : (want > 128 ? 128 : want);
+    }
+    return (int)(want < cap ? want : cap);
 }
 
 static int sweep_grid(int64_t n, int F, int* rows_per_sweep) {
@@ -885,6 +1313,47 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
 
     const CacheWindow cw = cache_window(g, L.F);
     const double sigma1 = 1.0 / sqrt((double)g->n);
+    const int fused_nb = fused_blocks<V>(g, L);
+    if (fused_nb > 0) {
+        FusedArgs<V> fa{};
+        fa.st = g->stats;
+        fa.rp = g->row_ptr;
+        fa.col = g->col_idx;
+        fa.w = g->weights;
+        fa.diag = diag;
+        fa.perm = g->perm;
+        fa.hrow = g->hrow;
+        fa.heavy_min = g->heavy_min;
+        fa.R0 = Rb[0];
+        fa.R1 = Rb[1];
+        fa.R2 = Rb[2];
+        // lane groups of at least 8 lanes: a group loads 8 column indices per
+        // round (its lanes beyond the row's F quads only load indices)
+        fa.F = L.F;
+        fa.G = L.F < 8 ? 8 : L.F;
+        fa.K = 64 / fa.G;
+        fa.ld = L.ld;
+        fa.nv = nv;
+        fa.m = m;
+        fa.rw = fa.K;
+        fa.vm = L.vm;
+        fa.seed = seed;
+        fa.sigma1 = sigma1;
+        fa.eps_bd = kEpsBreakdown;
+        fa.alpha = alpha;
+        fa.beta = beta;
+        fa.steps = steps;
+        fa.part = (double*)(ws + L.off_fused);
+        fa.bar = (unsigned*)(ws + L.off_bar);
+        fa.dstat = dstat;
+        fa.cw = cw;
+        hipLaunchKernelGGL(fused_reset, dim3(1), dim3(64), 0, st, fa.bar);
+        SLAQ_LAUNCHED();
+        SLAQ_TIMED("lanczos_fused", st,
+                   SLAQ_DISPATCH(mode, weighted, lanczos_fused, dim3(fused_nb), dim3(256), 0, st, fa));
+        SLAQ_LAUNCHED();
+        return SLAQ_OK;
+    }
     hipLaunchKernelGGL(state_init<V>, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef,
                        g->stats);
     SLAQ_LAUNCHED();

@@ -20,15 +20,24 @@ __global__ void __launch_bounds__(64) ritz_kernel(const double* __restrict__ alp
     double* d = lds + t;
     double* e = lds + B * m + t;
     double* u = lds + 2 * B * m + t;
+    // the block's coefficients into LDS with all threads at once (coalesced,
+    // every load in flight together), then one thread per probe
+    {
+        const int64_t first = (int64_t)blockIdx.x * B * m;
+        const int64_t count = (int64_t)(nv - blockIdx.x * B < B ? nv - blockIdx.x * B : B) * m;
+        for (int64_t x = t; x < count; x += B) {
+            const int pl = (int)(x / m), i = (int)(x % m);
+            lds[i * B + pl] = alpha[first + x];
+            lds[B * m + i * B + pl] = beta[first + x];
+        }
+    }
+    __syncthreads();
     if (p >= nv) return;
     int k = steps[p];
     k = k < 0 ? 0 : (k > m ? m : k);
     bool finite = true;
-    for (int i = 0; i < k; ++i) {
-        d[i * B] = alpha[(int64_t)p * m + i];
-        e[i * B] = i + 1 < k ? beta[(int64_t)p * m + i] : 0.0;
-        finite = finite && isfinite(d[i * B]) && isfinite(e[i * B]);
-    }
+    if (k > 0) e[(k - 1) * B] = 0.0;
+    for (int i = 0; i < k; ++i) finite = finite && isfinite(d[i * B]) && isfinite(e[i * B]);
     if (!finite) raise_status(dstat, SLAQ_STATUS_NONFINITE);
     if (tridiag_eig_first_row(d, e, u, k, B) < 0) raise_status(dstat, SLAQ_STATUS_NO_CONVERGENCE);
     for (int i = 0; i < m; ++i) {

@@ -49,7 +49,15 @@ __device__ inline int tridiag_eig_first_row(double* d, double* e, double* u, int
         const double mu = dh - eh * eh / denom;
         double x = d[lo * stride] - mu;
         double z = e[lo * stride];
+        // the bulge chase carries d[k], e[k] and u[k] in registers from one
+        // rotation to the next (each sweep finalizes index k as it moves on);
+        // only the next index is loaded, so the loads do not sit on the
+        // dependent chain of the rotations
+        double a = d[lo * stride], b = e[lo * stride], u0 = u[lo * stride];
         for (int k = lo; k < hi; ++k) {
+            const double dd = d[(k + 1) * stride];
+            const double u1 = u[(k + 1) * stride];
+            const double en = k + 1 < hi ? e[(k + 1) * stride] : 0.0;
             // rotation with s*x + c*z = 0
             double c, s;
             if (z == 0.0) {
@@ -57,29 +65,31 @@ __device__ inline int tridiag_eig_first_row(double* d, double* e, double* u, int
                 s = 0.0;
             } else if (fabs(z) > fabs(x)) {
                 const double tau = -x / z;
-                s = 1.0 / sqrt(1.0 + tau * tau);
+                s = rsqrt(1.0 + tau * tau);  // one reciprocal square root, not a root and a division
                 c = s * tau;
             } else {
                 const double tau = -z / x;
-                c = 1.0 / sqrt(1.0 + tau * tau);
+                c = rsqrt(1.0 + tau * tau);
                 s = c * tau;
             }
             if (k > lo) e[(k - 1) * stride] = c * x - s * z;
-            const double a = d[k * stride], b = e[k * stride], dd = d[(k + 1) * stride];
             const double cc = c * c, ss = s * s, cs = c * s;
             d[k * stride] = a * cc - 2.0 * b * cs + dd * ss;
-            d[(k + 1) * stride] = a * ss + 2.0 * b * cs + dd * cc;
+            const double a_next = a * ss + 2.0 * b * cs + dd * cc;
             const double bn = (a - dd) * cs + b * (cc - ss);
-            e[k * stride] = bn;
-            if (k + 1 < hi) {
-                const double en = e[(k + 1) * stride];
-                z = -s * en;
-                e[(k + 1) * stride] = c * en;
-                x = bn;
-            }
-            const double u0 = u[k * stride], u1 = u[(k + 1) * stride];
             u[k * stride] = c * u0 - s * u1;
-            u[(k + 1) * stride] = s * u0 + c * u1;
+            const double u_next = s * u0 + c * u1;
+            if (k + 1 < hi) {
+                z = -s * en;
+                b = c * en;
+                x = bn;
+            } else {
+                e[k * stride] = bn;
+                d[(k + 1) * stride] = a_next;
+                u[(k + 1) * stride] = u_next;
+            }
+            a = a_next;
+            u0 = u_next;
         }
     }
     return sweeps;

@@ -31,6 +31,7 @@ SLAQ_ERR_NUMERIC = 3
 SLAQ_ERR_WORKSPACE = 4
 SLAQ_STATUS_NONFINITE = 1
 SLAQ_STATUS_NO_CONVERGENCE = 2
+SLAQ_STATUS_GRID = 4
 
 STATUS = {
     0: "SLAQ_OK", 1: "SLAQ_ERR_INVALID_ARG", 2: "SLAQ_ERR_NOT_SYMMETRIC", 3: "SLAQ_ERR_NUMERIC",
@@ -56,6 +57,7 @@ SIGNATURES = {
     "slaq_graph_set_schedule": [_vp, _int, _int, _vp],
     "slaq_graph_set_tile": [_vp, _int],
     "slaq_graph_set_cache_rows": [_vp, _i64],
+    "slaq_graph_set_fused": [_vp, _int],
     "slaq_graph_cache_rows": [_vp, ctypes.POINTER(_i64)],
     "slaq_graph_set_precision": [_vp, _int],
     "slaq_graph_precision": [_vp, ctypes.POINTER(_int)],
@@ -189,6 +191,10 @@ class Graph:
         r = _i64()
         _check(lib().slaq_graph_cache_rows(self.handle, ctypes.byref(r)))
         return r.value
+
+    def set_fused(self, blocks):
+        """slaq_graph_set_fused: -1 automatic, 0 never, 1..256 workgroups."""
+        _check(lib().slaq_graph_set_fused(self.handle, int(blocks)))
 
     def set_precision(self, precision):
         _check(lib().slaq_graph_set_precision(self.handle, precision))
