@@ -178,8 +178,10 @@ __device__ __forceinline__ void finish_beta(int t, int nv, int m, int j, const d
 
 // Degrees and D^-1/2 of one graph (thread per row), its non-isolated count
 // (LDS integer atomic) and the self-loops' share of tr L (§2: L_ii = 1 -
-// A_ii / D_ii), summed in thread order only when the graph has a loop.  Uses
-// red[0, B) and ends with a barrier.
+// A_ii / D_ii), summed in thread order only when the graph has a loop.  Rows
+// list their columns in ascending order without repeats (the CSR contract),
+// so a row's diagonal entry is found by binary search.  Uses red[0, B) and
+// ends with a barrier.
 __device__ __forceinline__ void degrees_and_loops(int t, int B, int n, const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, int64_t base,
                                                   float* __restrict__ dinv, double* red, int* s_nz, int* s_loops,
@@ -190,8 +192,13 @@ __device__ __forceinline__ void degrees_and_loops(int t, int B, int n, const int
         const int64_t s = rp[i], e = rp[i + 1], d = e - s;
         dinv[i] = d > 0 ? (float)(1.0 / sqrt((double)d)) : 0.0f;
         nonzero += d > 0 ? 1 : 0;
-        int self = 0;
-        for (int64_t k = s; k < e; ++k) self += (int64_t)col[k] == base + i ? 1 : 0;
+        int64_t lo = s, hi = e;  // first entry with column >= base + i
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)col[mid] < base + i) lo = mid + 1;
+            else hi = mid;
+        }
+        const int self = lo < e && (int64_t)col[lo] == base + i ? 1 : 0;
         if (self) {
             ++loops;
             share += (double)self / (double)d;
