@@ -69,7 +69,7 @@ def update_algorithmic_bytes(n, n_act, nv):
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
-def measured_traffic(args):
+def measured_traffic(args, settings=None):
     """HBM bytes per SpMM-stage launch from the committed FETCH_SIZE /
     WRITE_SIZE record of this workload (profiles/spmm_<workload>_traffic.json),
     or None when there is none for this workload and launch configuration
@@ -83,6 +83,8 @@ def measured_traffic(args):
     rec = json.load(open(path))
     if rec.get("digest") != kernel_sources_digest():
         return None
+    if rec.get("settings") != settings:
+        return None  # taken under another schedule
     return rec
 
 
@@ -373,6 +375,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="probe tile of the gather kernels in float4 words (0 = auto)")
     ap.add_argument("--heavy-min", type=int, default=0, help="row-schedule heavy threshold (0 = library default)")
     ap.add_argument("--piece", type=int, default=0, help="row-schedule piece size (0 = library default)")
+    ap.add_argument("--tune", default="cache", choices=("off", "cache", "full"),
+                    help="schedule: library defaults, the package's tuning cache (default), or tune on a miss")
+    ap.add_argument("--tune-cache", default=None, help="tuning cache file (default: the package's)")
     ap.add_argument("--cache-rows", type=int, default=-1,
                     help="hot window of the gathers, rows per column range (-1 = library default)")
     ap.add_argument("--closure-train", type=int, default=0, help="override the closure's training-graph count")
@@ -431,6 +436,16 @@ def main():
 
     # preallocated buffers: the timed step allocates nothing
     g0 = S.build_graph(rp, ci)
+    defaults = g0.settings()
+    tuned = None
+    if args.tune != "off" and not (args.heavy_min or args.piece or args.cache_rows != -1):
+        # the package's tuning cache for this GPU and shape (untimed set-up);
+        # --tune full times the candidates on a miss and records the winner
+        t1 = time.perf_counter()
+        tuned, hit = g0.autotune(nv, m, seed=args.seed, reps=1 if args.tune == "full" else 0,
+                                 cache_path=args.tune_cache or S.TUNING_CACHE)
+        log(f"schedule {'from the tuning cache' if hit else ('tuned' if args.tune == 'full' else 'default')}: "
+            f"{tuned} ({time.perf_counter() - t1:.1f} s)")
     if args.heavy_min or args.piece:
         sch0 = g0.schedule()
         g0.set_schedule(args.heavy_min or sch0["heavy_min"], args.piece or sch0["piece"])
@@ -459,6 +474,11 @@ def main():
             g.set_tile(args.tile)
         if args.cache_rows != -1:
             g.set_cache_rows(args.cache_rows)
+        if tuned is not None:
+            if (tuned["heavy_min"], tuned["piece"]) != (defaults["heavy_min"], defaults["piece"]):
+                g.set_schedule(tuned["heavy_min"], tuned["piece"])
+            g.set_cache_rows(tuned["cache_rows"])
+            g.set_fused(tuned["fused"])
         S.lanczos(g, nv, m, args.seed, workspace=ws, out=(alpha, beta, steps))
         S.ritz(alpha, beta, steps, out=(theta, tau2))
         S.signature(theta, tau2, n, tgrid, S.SLAQ_SIG_HEAT, out=heat)
@@ -510,7 +530,7 @@ def main():
     spmm_bytes = spmm_algorithmic_bytes(n, n_act, nnz, nv)
     upd_ms = stages["update"]["avg_ms"]
     upd_gbs = update_algorithmic_bytes(n, n_act, nv) / (upd_ms * 1e-3) / 1e9 if upd_ms else None
-    rec = measured_traffic(args)
+    rec = measured_traffic(args, graphs[0].settings())
     traffic = rec["bytes_per_launch"] if rec else None
     upd_traffic = rec.get("update_bytes_per_launch") if rec else None
     # the Lanczos loop alone (SpMM stage, update, finalizes, or the single
@@ -594,7 +614,7 @@ def main():
                    "nt": nt, "outputs": ["heat", "wave", "vnge"], "laplacian": "normalized",
                    "generator": spec, "permuted": args.permute, "hipgraph": args.graph, "n_nonisolated": n_act,
                    "relabeled": graphs[0].relabeled(), "schedule": graphs[0].schedule(),
-                   "tile_quads": args.tile, "cache_rows": args.cache_rows},
+                   "tile_quads": args.tile, "cache_rows": args.cache_rows, "tuned": tuned},
         "roofline": {"bound": "hbm", "kernel": unit_kernel, "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "bytes_per_launch": unit_bytes, "avg_launch_ms": unit_ms,

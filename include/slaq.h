@@ -173,6 +173,31 @@ slaq_status slaq_graph_cache_rows(slaq_graph_t g, int64_t* rows);
  * SLAQ_STATUS_GRID). */
 slaq_status slaq_graph_set_fused(slaq_graph_t g, int blocks);
 
+/* Autotuner of the schedule above (row schedule heavy_min / piece, hot window,
+ * single launch and its workgroups): none of these changes what §3.1's
+ * recurrence computes, only where its work runs, so results differ at most by
+ * rounding order.  Times each candidate with HIP events over `reps` Lanczos
+ * runs after one untimed run (graphs of 2^22 stored entries and more on their
+ * first 4 steps), searching coordinate-wise from the current settings, and
+ * leaves the fastest set on the graph.  alpha, beta, steps and workspace are
+ * the caller's slaq_lanczos buffers, used as scratch (overwritten); the
+ * workspace should hold slaq_graph_autotune_workspace() bytes (a candidate
+ * that needs more is skipped).  Waits for `stream`.  cache_path (NULL = no
+ * cache): a JSON file mapping "<GPU arch>|<shape bucket>" (Laplacian,
+ * precision, relabelling, padded nv, ceil(log2) of n and nnz) to the chosen
+ * settings; a hit applies them without timing (*from_cache = 1), a miss tunes
+ * and rewrites the file with the new entry.  A file that is not a cache is
+ * an error (SLAQ_ERR_INVALID_ARG), as is one that cannot be written.
+ * reps = 0: cache lookup only (a miss leaves the graph as it is). */
+slaq_status slaq_graph_autotune(slaq_graph_t g, int nv, int m, uint64_t seed, double* alpha,
+                                double* beta, int32_t* steps, void* workspace,
+                                size_t workspace_bytes, int reps, const char* cache_path,
+                                int* from_cache, void* stream);
+slaq_status slaq_graph_autotune_workspace(slaq_graph_t g, int nv, int m, size_t* bytes);
+/* The graph's current schedule settings (any output may be NULL). */
+slaq_status slaq_graph_settings(slaq_graph_t g, int* heavy_min, int* piece, int64_t* cache_rows,
+                                int* fused);
+
 /* Precision of the Lanczos vectors of this graph.  Default: FP32 for the
  * normalized Laplacian (spectrum in [0, 2]; GPU and FP64 results agree to
  * ~1e-5 relative), FP64 for the combinatorial one, whose spectrum spans

@@ -3,7 +3,7 @@
     python -m paper_2003_01282_amd.profsum stats <dir>      # --kernel-trace --stats
     python -m paper_2003_01282_amd.profsum pmc <dir>        # --pmc runs
     python -m paper_2003_01282_amd.profsum calls <dir> <name>   # every launch of a kernel (--kernel-trace)
-    python -m paper_2003_01282_amd.profsum traffic <fetch_dir> <write_dir> <copy_bytes> <out.json>
+    python -m paper_2003_01282_amd.profsum traffic <fetch_dir> <write_dir> <copy_bytes> <out.json> [settings]
 
 `stats` prints calls and average/total duration per kernel from
 *_kernel_stats.csv; `pmc` averages every counter column of
@@ -107,8 +107,11 @@ def calibration_dispatch(values, copy_bytes):
     raise SystemExit(f"no calibration copy of {copy_bytes} bytes among {len(values)} copy dispatches")
 
 
-def traffic(fetch_dir, write_dir, copy_bytes, out_json):
-    rec = {"kernels": {}, "digest": kernel_sources_digest()}
+def traffic(fetch_dir, write_dir, copy_bytes, out_json, settings=None):
+    """settings: the graph's schedule settings during the runs (as bench.py
+    reports them in config.tuned / slaq_graph_settings); a bench run under
+    other settings does not use the record."""
+    rec = {"kernels": {}, "digest": kernel_sources_digest(), "settings": settings}
     per_launch = 0.0
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         t = pmc_table(d)
@@ -138,6 +141,7 @@ if __name__ == "__main__":
     elif cmd == "calls":
         calls(sys.argv[2], sys.argv[3])
     elif cmd == "traffic":
-        traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5])
+        traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5],
+                json.loads(sys.argv[6]) if len(sys.argv) > 6 else None)
     else:
         raise SystemExit(f"unknown command {cmd}")

@@ -58,6 +58,11 @@ SIGNATURES = {
     "slaq_graph_set_tile": [_vp, _int],
     "slaq_graph_set_cache_rows": [_vp, _i64],
     "slaq_graph_set_fused": [_vp, _int],
+    "slaq_graph_autotune": [_vp, _int, _int, ctypes.c_uint64, _vp, _vp, _vp, _vp, _sz, _int, ctypes.c_char_p,
+                            ctypes.POINTER(_int), _vp],
+    "slaq_graph_autotune_workspace": [_vp, _int, _int, ctypes.POINTER(_sz)],
+    "slaq_graph_settings": [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_i64),
+                            ctypes.POINTER(_int)],
     "slaq_graph_cache_rows": [_vp, ctypes.POINTER(_i64)],
     "slaq_graph_set_precision": [_vp, _int],
     "slaq_graph_precision": [_vp, ctypes.POINTER(_int)],
@@ -196,6 +201,30 @@ class Graph:
         """slaq_graph_set_fused: -1 automatic, 0 never, 1..256 workgroups."""
         _check(lib().slaq_graph_set_fused(self.handle, int(blocks)))
 
+    def settings(self):
+        """slaq_graph_settings -> {heavy_min, piece, cache_rows, fused}."""
+        hm, pc, cr, fu = _int(), _int(), _i64(), _int()
+        _check(lib().slaq_graph_settings(self.handle, ctypes.byref(hm), ctypes.byref(pc), ctypes.byref(cr),
+                                         ctypes.byref(fu)))
+        return {"heavy_min": hm.value, "piece": pc.value, "cache_rows": cr.value, "fused": fu.value}
+
+    def autotune(self, nv, m, seed=0, reps=2, cache_path=None, stream=None):
+        """slaq_graph_autotune with buffers of its own; returns (settings,
+        from_cache)."""
+        dev = self._keep["row_ptr"].device
+        b = _sz()
+        _check(lib().slaq_graph_autotune_workspace(self.handle, nv, m, ctypes.byref(b)))
+        ws = _empty_aligned(b.value, dev)
+        a = torch.empty((nv, m), dtype=torch.float64, device=dev)
+        be = torch.empty_like(a)
+        st = torch.empty(nv, dtype=torch.int32, device=dev)
+        hit = _int()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(lib().slaq_graph_autotune(self.handle, nv, m, ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(a),
+                                         _ptr(be), _ptr(st), _ptr(ws), ws.numel(), reps, path, ctypes.byref(hit),
+                                         _stream(stream)))
+        return self.settings(), bool(hit.value)
+
     def set_precision(self, precision):
         _check(lib().slaq_graph_set_precision(self.handle, precision))
 
@@ -289,6 +318,8 @@ def lanczos(g, nv, m, seed, workspace=None, out=None, stream=None):
 
 
 NOALLOC_WORKSPACE_BYTES = 64 << 20
+# schedule tuning cache shipped with the package (slaq_graph_autotune's JSON)
+TUNING_CACHE = Path(__file__).resolve().parent / "tuning" / "schedules.json"
 
 
 def lanczos_noalloc(g, nv, m, seed, out=None, stream=None):

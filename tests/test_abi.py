@@ -46,6 +46,8 @@ def test_host_side_argument_errors():
     assert L.slaq_lanczos_noalloc(None, 4, 4, 1, None, None, None, None) == 1
     assert L.slaq_graph_set_cache_rows(None, 0) == 1
     assert L.slaq_graph_set_fused(None, -1) == 1
+    assert L.slaq_graph_autotune(None, 4, 4, 1, None, None, None, None, 0, 1, None, None, None) == 1
+    assert L.slaq_graph_settings(None, None, None, None, None) == 1
     assert L.slaq_signature(None, None, 4, 4, 10, None, 8, 0, None, None) == 1
 
 
