@@ -168,13 +168,16 @@ def train(net, data, epochs=20, batch=1024, lr=1e-3, seed=0, log=None, first_epo
     for ep in range(first_epoch, first_epoch + epochs):
         gen.manual_seed(epoch_seed(seed, ep))
         perm = torch.randperm(P, device="cuda", generator=gen)
-        tot, nb = 0.0, 0
+        # the epoch's loss is summed on the device and read once per epoch,
+        # so the minibatch launches queue without a host wait between them
+        tot = torch.zeros(1, dtype=torch.float64, device="cuda")
+        nb = 0
         for s in range(0, P, batch):
             idx = perm[s:s + batch]
             net.train_step(data.x[idx].contiguous(), data.y[idx].contiguous(), lr, loss=loss)
-            tot += float(loss.item())
+            tot += loss
             nb += 1
-        hist.append(tot / max(nb, 1))
+        hist.append(float(tot.item()) / max(nb, 1))
         if log:
             log(f"epoch {ep} loss {hist[-1]:.3e}")
         if checkpoint is not None:
