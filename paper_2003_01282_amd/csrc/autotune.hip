@@ -21,11 +21,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <map>
 #include <string>
 #include <vector>
 
 #include "common.hpp"
+#include "tuning_cache.hpp"
 
 namespace slaq {
 
@@ -57,105 +57,6 @@ std::string shape_key(const slaq_graph_s* g, int nv) {
     return buf;
 }
 
-// ---- the cache file: a flat JSON object of objects with numeric fields ----
-void skip_ws(const char*& s) {
-    while (*s == ' ' || *s == '\n' || *s == '\r' || *s == '\t') ++s;
-}
-
-bool parse_string(const char*& s, std::string& out) {
-    skip_ws(s);
-    if (*s != '"') return false;
-    ++s;
-    out.clear();
-    while (*s && *s != '"') {
-        if (*s == '\\' && s[1]) ++s;
-        out.push_back(*s++);
-    }
-    if (*s != '"') return false;
-    ++s;
-    return true;
-}
-
-bool expect(const char*& s, char c) {
-    skip_ws(s);
-    if (*s != c) return false;
-    ++s;
-    return true;
-}
-
-// {"key": {"field": number, ...}, ...}; false on anything else
-bool parse_cache(const std::string& text, std::map<std::string, std::map<std::string, double>>& out) {
-    const char* s = text.c_str();
-    if (!expect(s, '{')) return false;
-    skip_ws(s);
-    if (*s == '}') return true;
-    for (;;) {
-        std::string key;
-        if (!parse_string(s, key) || !expect(s, ':') || !expect(s, '{')) return false;
-        std::map<std::string, double> fields;
-        skip_ws(s);
-        if (*s != '}') {
-            for (;;) {
-                std::string name;
-                if (!parse_string(s, name) || !expect(s, ':')) return false;
-                skip_ws(s);
-                char* end = nullptr;
-                const double v = std::strtod(s, &end);
-                if (end == s) return false;
-                s = end;
-                fields[name] = v;
-                skip_ws(s);
-                if (*s == ',') {
-                    ++s;
-                    continue;
-                }
-                break;
-            }
-        }
-        if (!expect(s, '}')) return false;
-        out[key] = fields;
-        skip_ws(s);
-        if (*s == ',') {
-            ++s;
-            continue;
-        }
-        break;
-    }
-    return expect(s, '}');
-}
-
-bool read_file(const char* path, std::string& text) {
-    FILE* f = std::fopen(path, "rb");
-    if (!f) return false;
-    char buf[4096];
-    size_t k;
-    text.clear();
-    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
-    std::fclose(f);
-    return true;
-}
-
-bool write_cache(const char* path, const std::map<std::string, std::map<std::string, double>>& entries) {
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE* f = std::fopen(tmp.c_str(), "wb");
-    if (!f) return false;
-    std::fprintf(f, "{");
-    bool first = true;
-    for (const auto& e : entries) {
-        std::fprintf(f, "%s\n \"%s\": {", first ? "" : ",", e.first.c_str());
-        bool ff = true;
-        for (const auto& kv : e.second) {
-            std::fprintf(f, "%s\"%s\": %.17g", ff ? "" : ", ", kv.first.c_str(), kv.second);
-            ff = false;
-        }
-        std::fprintf(f, "}");
-        first = false;
-    }
-    std::fprintf(f, "\n}\n");
-    const bool ok = std::fclose(f) == 0;
-    return ok && std::rename(tmp.c_str(), path) == 0;
-}
-
 slaq_status apply(slaq_graph_t g, const Setting& s, hipStream_t st) {
     if (s.heavy_min != g->heavy_min || s.piece != g->piece) {
         const slaq_status r = slaq_graph_set_schedule(g, s.heavy_min, s.piece, st);
@@ -185,11 +86,11 @@ slaq_status slaq_graph_autotune(slaq_graph_t g, int nv, int m, uint64_t seed, do
     hipStream_t st = (hipStream_t)stream;
     if (from_cache) *from_cache = 0;
     const std::string key = arch_name() + "|" + shape_key(g, nv);
-    std::map<std::string, std::map<std::string, double>> entries;
+    tuning::Entries entries;
     if (cache_path) {
         std::string text;
-        if (read_file(cache_path, text))
-            SLAQ_REQUIRE(parse_cache(text, entries), SLAQ_ERR_INVALID_ARG, "tuning cache %s is not a valid cache file",
+        if (tuning::read_file(cache_path, text))
+            SLAQ_REQUIRE(tuning::parse_cache(text, entries), SLAQ_ERR_INVALID_ARG, "tuning cache %s is not a valid cache file",
                          cache_path);
         auto it = entries.find(key);
         if (it != entries.end()) {
@@ -293,7 +194,7 @@ slaq_status slaq_graph_autotune(slaq_graph_t g, int nv, int m, uint64_t seed, do
         f["ms"] = best.ms;
         f["trials"] = (double)trials.size() + 1;
         entries[key] = f;
-        SLAQ_REQUIRE(write_cache(cache_path, entries), SLAQ_ERR_INVALID_ARG, "cannot write tuning cache %s",
+        SLAQ_REQUIRE(tuning::write_cache(cache_path, entries), SLAQ_ERR_INVALID_ARG, "cannot write tuning cache %s",
                      cache_path);
     }
     return SLAQ_OK;
