@@ -299,7 +299,9 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                 int64_t kk = s;
                 // kBatchUnroll column ids, then their LDS reads, are in flight at
-                // once; the products are added in nonzero order as below
+                // once; the products are added in nonzero order as below.  Row
+                // offsets use the full-rate 24-bit multiply (rows and quads per
+                // row are far below 2^24; the 32-bit one is quarter rate)
                 for (; kk + kBatchUnroll <= e; kk += kBatchUnroll) {
                     // a column outside the graph reads the zero row n: ignored
                     unsigned c[kBatchUnroll];
@@ -307,7 +309,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                     for (int u = 0; u < kBatchUnroll; ++u) c[u] = min((unsigned)(int)(col[kk + u] - base), (unsigned)n);
                     float4 x[kBatchUnroll];
 #pragma unroll
-                    for (int u = 0; u < kBatchUnroll; ++u) x[u] = R[c[u] * ldq + q];
+                    for (int u = 0; u < kBatchUnroll; ++u) x[u] = R[__umul24(c[u], (unsigned)ldq) + q];
 #pragma unroll
                     for (int u = 0; u < kBatchUnroll; ++u) {
                         acc.x += x[u].x;
@@ -318,7 +320,7 @@ __global__ void __launch_bounds__(B) batch_slq(BatchArgs a) {
                 }
                 for (; kk < e; ++kk) {
                     const unsigned c = min((unsigned)(int)(col[kk] - base), (unsigned)n);
-                    const float4 x = R[c * ldq + q];
+                    const float4 x = R[__umul24(c, (unsigned)ldq) + q];
                     acc.x += x.x;
                     acc.y += x.y;
                     acc.z += x.z;
