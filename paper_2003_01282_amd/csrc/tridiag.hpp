@@ -58,14 +58,26 @@ __device__ inline int tridiag_eig_first_row(double* d, double* e, double* u, int
             const double dd = d[(k + 1) * stride];
             const double u1 = u[(k + 1) * stride];
             const double en = k + 1 < hi ? e[(k + 1) * stride] : 0.0;
-            // rotation with s*x + c*z = 0
+            // rotation with s*x + c*z = 0: the larger of |c|, |s| positive,
+            // both from one reciprocal square root of x^2 + z^2 (no division;
+            // a ratio-based form guards squares that would over- or underflow)
             double c, s;
+            const double r2 = x * x + z * z;
             if (z == 0.0) {
                 c = 1.0;
                 s = 0.0;
+            } else if (r2 > 1e-290 && r2 < 1e290) {
+                const double ri = rsqrt(r2);
+                if (fabs(z) > fabs(x)) {
+                    s = fabs(z) * ri;
+                    c = -x * copysign(ri, z);
+                } else {
+                    c = fabs(x) * ri;
+                    s = -z * copysign(ri, x);
+                }
             } else if (fabs(z) > fabs(x)) {
                 const double tau = -x / z;
-                s = rsqrt(1.0 + tau * tau);  // one reciprocal square root, not a root and a division
+                s = rsqrt(1.0 + tau * tau);
                 c = s * tau;
             } else {
                 const double tau = -z / x;
