@@ -147,9 +147,16 @@ def bench_batched(args):
     log(f"{len(gs)} graphs, sum n={union.n}, nnz={union.nnz} in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda", 0)
     tgrid = torch.from_numpy(inputs.t_grid(256)).to(dev)
-    b = S.batch_plan(union, off, nv=nv, m=m, nt=256)
-    tuned = S.batch_autotune(b, tgrid, reps=3)
-    log(f"autotuned buckets {b.buckets()} -> {tuned}")
+    growth = 2.0
+    if args.tune_edges:
+        rp_d = torch.from_numpy(union.row_ptr).to(dev)
+        ci_d = torch.from_numpy(union.col_idx).to(dev)
+        b, growth, tms = S.batch_autotune_edges(rp_d, ci_d, off, nv=nv, m=m, nt=256, t=tgrid, reps=3)
+        log(f"edge tuner: growth {growth} ({tms:.3f} ms), buckets {b.buckets()}")
+    else:
+        b = S.batch_plan(union, off, nv=nv, m=m, nt=256)
+        tuned = S.batch_autotune(b, tgrid, reps=3)
+        log(f"autotuned buckets {b.buckets()} -> {tuned}")
     out = {"heat": torch.empty((b.G, 256), dtype=torch.float64, device=dev),
            "vnge": torch.empty(b.G, dtype=torch.float64, device=dev)}
     for _ in range(args.warmup):
@@ -194,7 +201,7 @@ def bench_batched(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched_small_graphs_slq", "graphs": b.G, "sum_n": union.n, "nnz": union.nnz,
-                   "nv": nv, "m": m, "nt": 256, "buckets": b.buckets()},
+                   "nv": nv, "m": m, "nt": 256, "bucket_growth": growth, "buckets": b.buckets()},
         "accuracy": {"reference": "m=30 same probes", "rel_l2_median": float(np.median(rel)),
                      "rel_l2_max": float(rel.max()), "fraction_at_or_below_1e-3": ok},
         "graphs_per_s_all": gps_all,
@@ -390,6 +397,8 @@ def main():
     ap.add_argument("--closure-lr", type=float, default=2e-3, help="closure training learning rate (Adam)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (calibrates hardware byte counters)")
+    ap.add_argument("--tune-edges", action="store_true",
+                    help="batched: tune the LDS bucket edges (growth 2, 1.5, 3) as well as the workgroup sizes")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of one step captured into a HIP graph (launch-bound workloads)")
     ap.add_argument("--permute", action="store_true",

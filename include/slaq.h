@@ -375,13 +375,31 @@ slaq_status slaq_vnge_slq(const double* alpha, const double* beta, const int32_t
  *
  * slaq_batch_autotune times every workgroup size in {128, 256, 512, 1024}
  * per bucket (median of reps runs, HIP events) and keeps the fastest; the
- * chosen sizes are returned in blocks_out[n_buckets] (optional). */
+ * chosen sizes are returned in blocks_out[n_buckets] (optional).
+ *
+ * slaq_batch_plan_grown is slaq_batch_plan with the LDS buckets' node-count
+ * edges growing by `growth` (in [1.25, 8]; slaq_batch_plan uses 2: 64, 128,
+ * 256, ...).  slaq_batch_autotune_edges plans the batch with growth 2, 1.5
+ * and 3, autotunes each plan's workgroup sizes, times `reps` full runs of it
+ * (heat at the nt times of t and VNGE, after one untimed run; HIP events,
+ * median) and returns the fastest plan in *out (the others are destroyed),
+ * its growth and time.  It allocates and frees its own output buffers and
+ * waits for `stream`. */
 enum { SLAQ_BATCH_GRAPH = 1u };
 typedef struct slaq_batch_s* slaq_batch_t;
 slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
                             const int64_t* node_off_dev, const int64_t* row_ptr,
                             const int32_t* col_idx, int nv, int m, int nt,
                             const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out);
+slaq_status slaq_batch_plan_grown(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
+                                  const int64_t* node_off_dev, const int64_t* row_ptr,
+                                  const int32_t* col_idx, int nv, int m, int nt, double growth,
+                                  const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out);
+slaq_status slaq_batch_autotune_edges(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
+                                      const int64_t* node_off_dev, const int64_t* row_ptr,
+                                      const int32_t* col_idx, int nv, int m, int nt, const double* t,
+                                      int reps, double* growth_out, float* ms_out, slaq_batch_t* out,
+                                      void* stream);
 slaq_status slaq_batch_buckets(slaq_batch_t b, int* n_buckets, int* n_hi, int* blocks, int* graphs,
                                int* in_lds);
 slaq_status slaq_batch_run(slaq_batch_t b, uint64_t seed, const double* t, double* heat, double* vnge,

@@ -774,7 +774,16 @@ extern "C" {
 slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
                             const int64_t* node_off_dev, const int64_t* row_ptr, const int32_t* col_idx, int nv,
                             int m, int nt, const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out) {
+    return slaq_batch_plan_grown(n_graphs, node_off, nnz_off, node_off_dev, row_ptr, col_idx, nv, m, nt, 2.0,
+                                 bucket_blocks, n_buckets_cfg, out);
+}
+
+slaq_status slaq_batch_plan_grown(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
+                                  const int64_t* node_off_dev, const int64_t* row_ptr, const int32_t* col_idx,
+                                  int nv, int m, int nt, double growth, const int* bucket_blocks, int n_buckets_cfg,
+                                  slaq_batch_t* out) {
     clear_error();
+    SLAQ_REQUIRE(growth >= 1.25 && growth <= 8.0, SLAQ_ERR_INVALID_ARG, "bucket growth must be in [1.25, 8]");
     SLAQ_REQUIRE(out, SLAQ_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     SLAQ_REQUIRE(n_graphs >= 1 && node_off && nnz_off && node_off_dev && row_ptr && col_idx, SLAQ_ERR_INVALID_ARG,
@@ -794,14 +803,16 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
                  "a batch holds fewer than 2^31 nodes in all (column ids are int32)");
     SLAQ_REQUIRE(n_graphs * nv * m <= INT32_MAX, SLAQ_ERR_UNSUPPORTED,
                  "G * nv * m must stay below 2^31 (got %lld)", (long long)(n_graphs * nv * m));
-    // LDS buckets by doubling node counts up to the largest probe block that
-    // stays in LDS, then one global bucket for every larger graph (a single
+    // LDS buckets by node counts growing from 64 by `growth` (doubling by
+    // default) up to the largest probe block that stays in LDS, then one global bucket for every larger graph (a single
     // persistent launch pulling them largest first keeps the CUs busy where
     // size classes of their own would each leave most of the chip idle)
     const int64_t lds_cap_n = lds_node_cap(nv);
     std::vector<int64_t> edges = {0, std::min<int64_t>(64, lds_cap_n)};
-    while (edges.back() < nmax && edges.back() < lds_cap_n)
-        edges.push_back(std::min<int64_t>(edges.back() * 2, lds_cap_n));
+    while (edges.back() < nmax && edges.back() < lds_cap_n) {
+        const int64_t next = std::max<int64_t>(edges.back() + 1, (int64_t)std::ceil((double)edges.back() * growth));
+        edges.push_back(std::min<int64_t>(next, lds_cap_n));
+    }
     if (edges.back() < nmax) edges.push_back(nmax);
     slaq_batch_s* b = new (std::nothrow) slaq_batch_s();
     SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "out of host memory");
@@ -1128,6 +1139,79 @@ slaq_status slaq_batch_set_seeds(slaq_batch_t b, const uint64_t* seeds) {
     clear_error();
     SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
     b->seeds = seeds;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_autotune_edges(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
+                                      const int64_t* node_off_dev, const int64_t* row_ptr, const int32_t* col_idx,
+                                      int nv, int m, int nt, const double* t, int reps, double* growth_out,
+                                      float* ms_out, slaq_batch_t* out, void* stream) {
+    clear_error();
+    SLAQ_REQUIRE(out && t, SLAQ_ERR_INVALID_ARG, "NULL argument");
+    SLAQ_REQUIRE(reps >= 1 && reps <= 100, SLAQ_ERR_INVALID_ARG, "reps must be in [1, 100]");
+    SLAQ_REQUIRE(nt >= 1, SLAQ_ERR_INVALID_ARG, "need nt >= 1 time scales to time the runs");
+    *out = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    double *heat = nullptr, *vn = nullptr;
+    if (hipMalloc(&heat, (size_t)n_graphs * nt * sizeof(double)) != hipSuccess ||
+        hipMalloc(&vn, (size_t)n_graphs * sizeof(double)) != hipSuccess) {
+        if (heat) (void)hipFree(heat);
+        set_error("hipMalloc of the tuning outputs failed");
+        return SLAQ_ERR_HIP;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    slaq_status r = SLAQ_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        set_error("hipEventCreate failed");
+        r = SLAQ_ERR_HIP;
+    }
+    slaq_batch_t best = nullptr;
+    float best_ms = 1e30f;
+    double best_g = 2.0;
+    const double growths[] = {2.0, 1.5, 3.0};
+    for (double gr : growths) {
+        if (r != SLAQ_OK) break;
+        slaq_batch_t b = nullptr;
+        r = slaq_batch_plan_grown(n_graphs, node_off, nnz_off, node_off_dev, row_ptr, col_idx, nv, m, nt, gr,
+                                  nullptr, 0, &b);
+        if (r == SLAQ_OK) r = slaq_batch_autotune(b, t, heat, vn, reps, nullptr, nullptr, st);
+        std::vector<float> ts;
+        for (int k = 0; r == SLAQ_OK && k <= reps; ++k) {  // one untimed run first
+            if (hipEventRecord(e0, st) != hipSuccess) r = SLAQ_ERR_HIP;
+            if (r == SLAQ_OK)
+                r = slaq_batch_run(b, 12345, t, heat, vn, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st);
+            float ms = 0.0f;
+            if (r == SLAQ_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                r = SLAQ_ERR_HIP;
+            if (k > 0) ts.push_back(ms);
+        }
+        if (r != SLAQ_OK) {
+            if (b) slaq_batch_destroy(b);
+            break;
+        }
+        std::sort(ts.begin(), ts.end());
+        const float med = ts[ts.size() / 2];
+        if (med < best_ms) {
+            if (best) slaq_batch_destroy(best);
+            best = b;
+            best_ms = med;
+            best_g = gr;
+        } else {
+            slaq_batch_destroy(b);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(heat);
+    (void)hipFree(vn);
+    if (r != SLAQ_OK) {
+        if (best) slaq_batch_destroy(best);
+        return r;
+    }
+    *out = best;
+    if (growth_out) *growth_out = best_g;
+    if (ms_out) *ms_out = best_ms;
     return SLAQ_OK;
 }
 

@@ -75,6 +75,11 @@ SIGNATURES = {
     "slaq_signature": [_vp, _vp, _int, _int, _i64, _vp, _int, _int, _vp, _vp],
     "slaq_vnge": [_vp, _vp, _vp, _int, _int, _vp, _vp],
     "slaq_batch_plan": [_i64, _vp, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _int, ctypes.POINTER(_vp)],
+    "slaq_batch_plan_grown": [_i64, _vp, _vp, _vp, _vp, _vp, _int, _int, _int, ctypes.c_double, _vp, _int,
+                              ctypes.POINTER(_vp)],
+    "slaq_batch_autotune_edges": [_i64, _vp, _vp, _vp, _vp, _vp, _int, _int, _int, _vp, _int,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
+                                  ctypes.POINTER(_vp), _vp],
     "slaq_batch_buckets": [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp],
     "slaq_batch_run": [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
     "slaq_batch_set_seeds": [_vp, _vp],
@@ -490,46 +495,59 @@ class Batch:
             self.handle = None
 
 
-def batch_plan(union_csr, node_off, nv, m, nt, bucket_blocks=None, device="cuda"):
-    """slaq_batch_plan for a block-diagonal union (inputs.disjoint_union)."""
+def _plan(row_ptr, col_idx, goff, node_off, nnz_off, nv, m, nt, bucket_blocks, growth):
+    G = len(node_off) - 1
+    bb = None
+    nbb = 0
+    if bucket_blocks is not None:
+        bb = (ctypes.c_int * len(bucket_blocks))(*bucket_blocks)
+        nbb = len(bucket_blocks)
+    h = _vp()
+    _check(lib().slaq_batch_plan_grown(G, node_off.ctypes.data_as(_vp), nnz_off.ctypes.data_as(_vp), _ptr(goff),
+                                       _ptr(row_ptr), _ptr(col_idx), nv, m, nt, float(growth), bb, nbb,
+                                       ctypes.byref(h)))
+    return Batch(h, G, nv, m, nt, {"rp": row_ptr, "ci": col_idx, "goff": goff})
+
+
+def batch_plan(union_csr, node_off, nv, m, nt, bucket_blocks=None, device="cuda", growth=2.0):
+    """slaq_batch_plan (slaq_batch_plan_grown for growth != 2) for a
+    block-diagonal union (inputs.disjoint_union)."""
     import numpy as np
     node_off = np.ascontiguousarray(node_off, dtype=np.int64)
     nnz_off = np.ascontiguousarray(union_csr.row_ptr[node_off], dtype=np.int64)
     rp = torch.from_numpy(union_csr.row_ptr).to(device)
     ci = torch.from_numpy(union_csr.col_idx).to(device)
     goff = torch.from_numpy(node_off).to(device)
-    G = len(node_off) - 1
-    bb = None
-    nbb = 0
-    if bucket_blocks is not None:
-        bb = (ctypes.c_int * len(bucket_blocks))(*bucket_blocks)
-        nbb = len(bucket_blocks)
-    h = _vp()
-    _check(lib().slaq_batch_plan(G, node_off.ctypes.data_as(_vp), nnz_off.ctypes.data_as(_vp), _ptr(goff),
-                                 _ptr(rp), _ptr(ci), nv, m, nt, bb, nbb, ctypes.byref(h)))
-    return Batch(h, G, nv, m, nt, {"rp": rp, "ci": ci, "goff": goff})
+    return _plan(rp, ci, goff, node_off, nnz_off, nv, m, nt, bucket_blocks, growth)
 
 
-def batch_plan_device(row_ptr, col_idx, node_off, nv, m, nt, bucket_blocks=None):
-    """slaq_batch_plan for a block-diagonal union already on the device
-    (int64 row_ptr, int32 global col_idx; host int64 node offsets [G+1])."""
+def _device_union_offsets(row_ptr, col_idx, node_off):
     import numpy as np
     _dev(row_ptr, torch.int64, "row_ptr")
     _dev(col_idx, torch.int32, "col_idx")
     node_off = np.ascontiguousarray(node_off, dtype=np.int64)
-    dev = row_ptr.device
-    goff = torch.from_numpy(node_off).to(dev)
+    goff = torch.from_numpy(node_off).to(row_ptr.device)
     nnz_off = np.ascontiguousarray(row_ptr[goff].cpu().numpy(), dtype=np.int64)
+    return goff, node_off, nnz_off
+
+
+def batch_plan_device(row_ptr, col_idx, node_off, nv, m, nt, bucket_blocks=None, growth=2.0):
+    """slaq_batch_plan for a block-diagonal union already on the device
+    (int64 row_ptr, int32 global col_idx; host int64 node offsets [G+1])."""
+    goff, node_off, nnz_off = _device_union_offsets(row_ptr, col_idx, node_off)
+    return _plan(row_ptr, col_idx, goff, node_off, nnz_off, nv, m, nt, bucket_blocks, growth)
+
+
+def batch_autotune_edges(row_ptr, col_idx, node_off, nv, m, nt, t, reps=3, stream=None):
+    """slaq_batch_autotune_edges on a device union -> (plan, growth, ms): the
+    fastest of the bucket-edge growths 2, 1.5 and 3, workgroup sizes tuned."""
+    goff, node_off, nnz_off = _device_union_offsets(row_ptr, col_idx, node_off)
     G = len(node_off) - 1
-    bb = None
-    nbb = 0
-    if bucket_blocks is not None:
-        bb = (ctypes.c_int * len(bucket_blocks))(*bucket_blocks)
-        nbb = len(bucket_blocks)
-    h = _vp()
-    _check(lib().slaq_batch_plan(G, node_off.ctypes.data_as(_vp), nnz_off.ctypes.data_as(_vp), _ptr(goff),
-                                 _ptr(row_ptr), _ptr(col_idx), nv, m, nt, bb, nbb, ctypes.byref(h)))
-    return Batch(h, G, nv, m, nt, {"rp": row_ptr, "ci": col_idx, "goff": goff})
+    h, gr, ms = _vp(), ctypes.c_double(), ctypes.c_float()
+    _check(lib().slaq_batch_autotune_edges(G, node_off.ctypes.data_as(_vp), nnz_off.ctypes.data_as(_vp),
+                                           _ptr(goff), _ptr(row_ptr), _ptr(col_idx), nv, m, nt, _ptr(t), reps,
+                                           ctypes.byref(gr), ctypes.byref(ms), ctypes.byref(h), _stream(stream)))
+    return Batch(h, G, nv, m, nt, {"rp": row_ptr, "ci": col_idx, "goff": goff}), gr.value, ms.value
 
 
 def union_device(graphs):

@@ -49,6 +49,11 @@ def test_host_side_argument_errors():
     assert L.slaq_graph_autotune(None, 4, 4, 1, None, None, None, None, 0, 1, None, None, None) == 1
     assert L.slaq_graph_settings(None, None, None, None, None) == 1
     assert L.slaq_signature(None, None, 4, 4, 10, None, 8, 0, None, None) == 1
+    # bucket growth outside [1.25, 8], and a missing output, are refused first
+    assert L.slaq_batch_plan_grown(1, None, None, None, None, None, 4, 4, 1, 1.0, None, 0, ctypes.byref(h)) == 1
+    assert b"growth" in L.slaq_last_error()
+    assert L.slaq_batch_autotune_edges(1, None, None, None, None, None, 4, 4, 1, None, 3, None, None, None,
+                                       None) == 1
 
 
 def test_binding_refuses_host_tensors():

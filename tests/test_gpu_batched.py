@@ -113,6 +113,35 @@ def test_autotune_keeps_results():
     np.testing.assert_allclose(after, before, rtol=1e-6)
 
 
+def test_bucket_edge_growth_against_oracle(batch60):
+    """Plans with finer and coarser LDS bucket edges (growth 1.5 and 3) and
+    the edge tuner's pick: every graph still within tolerance of the oracle."""
+    gs, b2, t, _ = batch60
+    rp, ci = b2._keep["rp"], b2._keep["ci"]
+    off = b2._keep["goff"].cpu().numpy()
+    plans = {gr: S.batch_plan_device(rp, ci, off, nv=20, m=10, nt=T.size, growth=gr) for gr in (1.5, 3.0)}
+    tuned, growth, ms = S.batch_autotune_edges(rp, ci, off, nv=20, m=10, nt=T.size, t=t, reps=2)
+    print(f"\n[gpu] edge tuner picked growth {growth} ({ms:.3f} ms), buckets {tuned.buckets()}", flush=True)
+    assert growth in (1.5, 2.0, 3.0) and ms > 0.0
+    n_lds = {gr: sum(k["in_lds"] for k in p.buckets()) for gr, p in plans.items()}
+    assert n_lds[1.5] >= sum(k["in_lds"] for k in b2.buckets()) >= n_lds[3.0]
+    plans["tuned"] = tuned
+    ref = {}
+    for g, csr in enumerate(gs):
+        og = O.build_graph(csr.n, csr.row_ptr, csr.col_idx)
+        a, be, st = O.lanczos(og, 20, 10, 77 + g)
+        th, w2 = O.ritz(a, be, st)
+        ref[g] = (O.heat_trace(th, w2, csr.n, T), O.vnge(th, w2, csr.n, og.trace))
+    for name, p in plans.items():
+        out = S.batch_run(p, 77, t)
+        torch.cuda.synchronize()
+        heat, vn = out["heat"].cpu().numpy(), out["vnge"].cpu().numpy()
+        for g in range(len(gs)):
+            h, H = ref[g]
+            assert (np.abs(heat[g] - h) / np.abs(h)).max() <= TOL_HEAT_REL, (name, g)
+            assert abs(vn[g] - H) <= TOL_VNGE_REL * abs(H) + 1e-12, (name, g)
+
+
 def with_loops(csr, nodes):
     r = np.r_[np.repeat(np.arange(csr.n), np.diff(csr.row_ptr)), nodes]
     c = np.r_[csr.col_idx.astype(np.int64), nodes]
