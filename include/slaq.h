@@ -173,6 +173,18 @@ slaq_status slaq_graph_cache_rows(slaq_graph_t g, int64_t* rows);
  * SLAQ_STATUS_GRID). */
 slaq_status slaq_graph_set_fused(slaq_graph_t g, int blocks);
 
+/* Gathers of the first Lanczos step (stage kernels).  The first basis block
+ * is +-1 per probe times one scale per row (§3.1: Rademacher probes; X_1 =
+ * D^-1/2 R_1 for the normalized Laplacian), so with on = 1 (the default) the
+ * first step's SpMM reads a compact record per column (the row's sign bits
+ * and its scale, padded to a power of two: 8 bytes for up to 32 probes in
+ * FP32, 16 for up to 64, 32 for up to 224) instead of its row of vector
+ * values, and expands it in registers to the same values: results are
+ * bit-identical either way.  The records live in the workspace's third
+ * vector buffer, unused during the first step, so the workspace size does
+ * not change.  on = 0 gathers the FP32 rows in every step. */
+slaq_status slaq_graph_set_sign_step(slaq_graph_t g, int on);
+
 /* Autotuner of the schedule above (row schedule heavy_min / piece, hot window,
  * single launch and its workgroups): none of these changes what §3.1's
  * recurrence computes, only where its work runs, so results differ at most by

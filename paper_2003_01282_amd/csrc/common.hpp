@@ -149,6 +149,7 @@ struct slaq_graph_s {
     int tile_quads;          // probe tile of the gather kernels in 16-byte words (0 = automatic)
     int64_t cache_rows;      // hot window of the gathers, rows per column range (-1 = automatic)
     int fused;               // single-launch Lanczos: -1 automatic, 0 never, > 0 that many workgroups
+    int sign_step;           // first step's gathers from the compact sign records (1) or the rows (0)
     int precision;           // SLAQ_PREC_* of the Lanczos vectors
     hipStream_t stream;      // stream of the build (slaq_graph_info waits on it)
 };

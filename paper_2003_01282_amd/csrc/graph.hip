@@ -632,6 +632,7 @@ slaq_status slaq_build_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, con
     g->tile_quads = 0;
     g->cache_rows = -1;
     g->fused = -1;
+    g->sign_step = 1;
     g->precision = laplacian == SLAQ_LAP_COMBINATORIAL ? SLAQ_PREC_FP64 : SLAQ_PREC_FP32;
     g->n = n;
     g->nnz = nnz;
@@ -745,6 +746,14 @@ slaq_status slaq_graph_set_fused(slaq_graph_t g, int blocks) {
     SLAQ_REQUIRE(blocks >= -1 && blocks <= 256, SLAQ_ERR_INVALID_ARG,
                  "blocks must be -1 (automatic), 0 (never) or 1..256");
     g->fused = blocks;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_graph_set_sign_step(slaq_graph_t g, int on) {
+    clear_error();
+    SLAQ_REQUIRE(g, SLAQ_ERR_INVALID_ARG, "graph is NULL");
+    SLAQ_REQUIRE(on == 0 || on == 1, SLAQ_ERR_INVALID_ARG, "on must be 0 or 1");
+    g->sign_step = on;
     return SLAQ_OK;
 }
 

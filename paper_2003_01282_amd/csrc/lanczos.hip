@@ -45,6 +45,7 @@
 #include <cmath>
 
 #include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 #include "profile.hpp"
@@ -170,6 +171,88 @@ __device__ __forceinline__ Quad<V> gather(const Quad<V>* __restrict__ Rl, int32_
     return packed >= 0 ? *p : qload_nt(p);
 }
 
+// The first step's probe block in compact form.  R_1 is +-1 times one scale
+// per row, so its gathers need not read the FP32 rows: record i is a run of
+// 16-byte slots, each holding 4 - sizeof(V)/4 dwords of sign bits (bit p of
+// the probe's dword set for -1, as the probe generator draws them) and then
+// the row's value of +1 in X_1 (dinv_i for the normalized Laplacian, 1 for
+// D - A, 0 on rows without data).  A lane loads the one slot with its
+// probes' bits and the scale in a single 16-byte load (records take a power
+// of two of slots, so a gather touches one cache line, against
+// ceil(4 ld / 128) lines for the FP32 row) and expands it to exactly the
+// values of X_1 (probes at or past nv to 0).  The expansion waits until all
+// loads of a gather round are issued: expanding each slot right after its
+// load serializes the round and is slower than gathering the rows.  Measured
+// with nv = 100, first-step pieces / light rows: R-MAT 22 2.30 / 2.63 ms
+// against 2.34-2.42 / 3.29-3.32 ms gathering the rows, R-MAT 24 10.5 / 8.2
+// against 13.9 / 11.9 ms.
+struct SignRows {
+    const uint32_t* rec;
+    int rd, nv;  // record dwords, probes
+};
+
+// one 16-byte slot of a sign record, as loaded
+struct Slot {
+    uint32_t x, y, z, w;
+};
+
+// the lane's slot of record `packed` (the column, hint in its sign bit)
+template <typename V>
+__device__ __forceinline__ Slot sign_load(const SignRows& sr, int32_t packed, int quad) {
+    constexpr int E = Quad<V>::E, HW = 4 - (int)(sizeof(V) / 4);
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const int h = ((E * quad) >> 5) / HW;
+    const u4* r = (const u4*)(sr.rec + (int64_t)(packed & 0x7fffffff) * sr.rd) + h;
+    const u4 v = packed >= 0 ? *r : __builtin_nontemporal_load(r);
+    return Slot{v.x, v.y, v.z, v.w};
+}
+
+// the lane's E values of X_1 from its slot: the scale is never negative, so a
+// probe's value is the scale with its sign bit set from the probe's bit
+// (padding probes, p >= nv, are 0; an all-zero slot gives +0)
+template <typename V>
+__device__ __forceinline__ Quad<V> sign_expand(const Slot& v, const SignRows& sr, int quad) {
+    constexpr int E = Quad<V>::E, HW = 4 - (int)(sizeof(V) / 4);
+    const int p0 = E * quad, w = p0 >> 5, pos = w - (w / HW) * HW;
+    const uint32_t wd = pos == 0 ? v.x : (HW > 1 && pos == 1 ? v.y : v.z);
+    Quad<V> q;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t b = __builtin_amdgcn_ubfe(wd, (uint32_t)((p0 & 31) + e), 1u);
+        if constexpr (sizeof(V) == 4) {
+            q.v[e] = __uint_as_float(p0 + e < sr.nv ? (b << 31) | v.w : 0u);
+        } else {
+            q.v[e] = p0 + e < sr.nv ? __hiloint2double((int)((b << 31) | v.w), (int)v.z) : 0.0;
+        }
+    }
+    return q;
+}
+
+// What a gather loads: the lane's quad of the FP32 row, or (SG) the slot of
+// the first step's sign record, expanded only where the values are summed
+// (so the loads of a round stay in flight together).
+template <bool SG, typename V>
+using Fetched = typename std::conditional<SG, Slot, Quad<V>>::type;
+
+template <bool SG, typename V>
+__device__ __forceinline__ Fetched<SG, V> fetch(const Quad<V>* __restrict__ Rl, int32_t packed, int ms,
+                                                const SignRows& sr, int quad) {
+    if constexpr (SG) return sign_load<V>(sr, packed, quad);
+    else return gather(Rl, packed, ms);
+}
+
+template <bool SG, typename V>
+__device__ __forceinline__ Fetched<SG, V> fzero() {
+    if constexpr (SG) return Slot{0u, 0u, 0u, 0u};
+    else return qzero<V>();
+}
+
+template <bool SG, typename V>
+__device__ __forceinline__ Quad<V> expand(const Fetched<SG, V>& f, const SignRows& sr, int quad) {
+    if constexpr (SG) return sign_expand<V>(f, sr, quad);
+    else return f;
+}
+
 // The column ranges' first labels (device, from the build) and the hot
 // window (rows per range whose gathers stay cached); a window of at least n
 // rows caches every gather.
@@ -263,7 +346,8 @@ template <typename V>
 __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__ st, int laplacian, int nv, int F,
                                                   VecMap vm, int rows_per_sweep, uint64_t seed,
                                                   const V* __restrict__ diag,
-                                                  const int32_t* __restrict__ perm, Quad<V>* __restrict__ R) {
+                                                  const int32_t* __restrict__ perm, Quad<V>* __restrict__ R,
+                                                  uint32_t* __restrict__ rec, int rd) {
     constexpr int E = Quad<V>::E;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int quad = tid % F;
@@ -277,9 +361,17 @@ __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__
     const uint64_t word = (uint64_t)(p0 >> 6);
     const int bit0 = p0 & 63;
     for (int64_t i = row0; i < n; i += rows_per_sweep) {
-        if (diag[i] == V(0)) continue;
         const uint64_t id = perm ? (uint64_t)perm[i] : (uint64_t)i;
         const uint64_t z = splitmix64(seed, 64ull * id + word);
+        if (rec && (p0 & 31) == 0) {  // sign record of row i (every row: every gather reads written slots)
+            constexpr int HW = 4 - (int)(sizeof(V) / 4);
+            const int wi = p0 >> 5, h = wi / HW, pos = wi - h * HW;
+            uint32_t* slot = rec + i * rd + 4 * h;
+            slot[pos] = (uint32_t)(z >> bit0);
+            if (pos == 0)
+                *(V*)(slot + HW) = diag[i] == V(0) ? V(0) : (laplacian == SLAQ_LAP_NORMALIZED ? diag[i] : V(1));
+        }
+        if (diag[i] == V(0)) continue;
         const V one = laplacian == SLAQ_LAP_NORMALIZED ? diag[i] : V(1);  // X_1 = D^-1/2 v
         Quad<V> v;
 #pragma unroll
@@ -295,11 +387,12 @@ __global__ void __launch_bounds__(256) probe_init(const GraphStats* __restrict__
 // Gather-accumulate over nonzeros [k0, k1) of one row by the group of this
 // lane: the group loads up to G column indices (and their scale) at once and
 // broadcasts them with lane shuffles; gathers are issued four at a time.
-template <int MODE, bool WEIGHTED, typename V>
+template <int MODE, bool WEIGHTED, typename V, bool SG = false>
 __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t k1, int gbase, int gl, int G,
                                               const int32_t* __restrict__ col, const float* __restrict__ w,
                                               const V* __restrict__ diag, const Quad<V>* __restrict__ Rl,
-                                              int ms, bool lane_ok, const HotRanges& hr) {
+                                              int ms, bool lane_ok, const HotRanges& hr,
+                                              const SignRows& sr = SignRows{}, int quad = 0) {
     for (int64_t kb = k0; kb < k1; kb += G) {
         const int cnt = (int)((k1 - kb) < G ? (k1 - kb) : G);
         int32_t cl = 0;
@@ -313,21 +406,21 @@ __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t 
         for (; u + 4 <= cnt; u += 4) {
             int32_t c[4];
             V s[4];
-            Quad<V> x[4];
+            Fetched<SG, V> x[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 c[v] = __shfl(cl, gbase + u + v);
                 s[v] = __shfl(sl, gbase + u + v);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? gather(Rl, c[v], ms) : qzero<V>();
+            for (int v = 0; v < 4; ++v) x[v] = lane_ok ? fetch<SG, V>(Rl, c[v], ms, sr, quad) : fzero<SG, V>();
 #pragma unroll
-            for (int v = 0; v < 4; ++v) qfma(s[v], x[v], acc);
+            for (int v = 0; v < 4; ++v) qfma(s[v], expand<SG, V>(x[v], sr, quad), acc);
         }
         for (; u < cnt; ++u) {
             const int32_t c = __shfl(cl, gbase + u);
             const V s = __shfl(sl, gbase + u);
-            if (lane_ok) qfma(s, gather(Rl, c, ms), acc);
+            if (lane_ok) qfma(s, expand<SG, V>(fetch<SG, V>(Rl, c, ms, sr, quad), sr, quad), acc);
         }
     }
 }
@@ -337,7 +430,7 @@ __device__ __forceinline__ void group_segment(Quad<V>& acc, int64_t k0, int64_t 
 // blockIdx.x % 8 == x, which the dispatcher places on one XCD; each wave walks
 // a contiguous run of its range's pieces so the owning heavy row advances
 // incrementally.
-template <int MODE, bool WEIGHTED, typename V>
+template <int MODE, bool WEIGHTED, typename V, bool SG>
 __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict__ st,
                                                    const int64_t* __restrict__ segk,
                                                    const int64_t* __restrict__ segoff, int64_t cap,
@@ -346,7 +439,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                                                    const V* __restrict__ diag,
                                                    const Quad<V>* __restrict__ R,
                                                    Quad<V>* __restrict__ P, int F, VecMap vm, int G, int K, int piece,
-                                                   int tile0, int TQ, CacheWindow cw) {
+                                                   int tile0, int TQ, CacheWindow cw, SignRows sr) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
     const int tile = tile0 + (int)blockIdx.y;
@@ -400,7 +493,7 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
             for (; r + kPieceUnroll <= rounds; r += kPieceUnroll) {
                 int32_t c[kPieceUnroll];
                 V s[kPieceUnroll];
-                Quad<V> xv[kPieceUnroll];
+                Fetched<SG, V> xv[kPieceUnroll];
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v) {
                     const int u = (r + v) * K + gi;
@@ -411,16 +504,16 @@ __global__ void __launch_bounds__(256) spmm_pieces(const GraphStats* __restrict_
                 }
 #pragma unroll
                 for (int v = 0; v < kPieceUnroll; ++v)
-                    xv[v] = (lane_ok && s[v] != V(0)) ? gather(Rl, c[v], ms) : qzero<V>();
+                    xv[v] = (lane_ok && s[v] != V(0)) ? fetch<SG, V>(Rl, c[v], ms, sr, quad) : fzero<SG, V>();
 #pragma unroll
-                for (int v = 0; v < kPieceUnroll; ++v) qfma(s[v], xv[v], acc);
+                for (int v = 0; v < kPieceUnroll; ++v) qfma(s[v], expand<SG, V>(xv[v], sr, quad), acc);
             }
             for (; r < rounds; ++r) {
                 const int u = r * K + gi;
                 const int src = u < 64 ? u : 63;
                 const int32_t c = __shfl(cl, src);
                 const V s = __shfl(sl, src);
-                if (lane_ok && u < cnt) qfma(s, gather(Rl, c, ms), acc);
+                if (lane_ok && u < cnt) qfma(s, expand<SG, V>(fetch<SG, V>(Rl, c, ms, sr, quad), sr, quad), acc);
             }
         }
         // fixed-order tree over the K groups (lane + st*G)
@@ -536,7 +629,7 @@ __global__ void __launch_bounds__(256) spmm_heavy(const GraphStats* __restrict__
 // Every light row with data: w = sigma (L R_j)_i - tau R_{j-1}[i]; partial
 // R_j.w.  A wave takes windows of rw rows (row offsets loaded by its lanes at
 // once); group gi handles rows gi, gi+K, ... of the window.
-template <int MODE, bool WEIGHTED, typename V>
+template <int MODE, bool WEIGHTED, typename V, bool SG>
 __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ st, const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const float* __restrict__ w,
@@ -546,7 +639,8 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
                                                  const Quad<V>* __restrict__ Rp,
                                                  Quad<V>* __restrict__ W, const V* __restrict__ coef,
                                                  int has_prev, double* __restrict__ part, int nb, int F, VecMap vm,
-                                                 int G, int K, int ld, int rw, int tile0, int TQ, CacheWindow cw) {
+                                                 int G, int K, int ld, int rw, int tile0, int TQ, CacheWindow cw,
+                                                 SignRows sr) {
     constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
@@ -585,7 +679,8 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
             if (!in_group || t >= rw || i >= n || e == s) continue;  // isolated: nothing stored
             if (e - s >= heavy_min) continue;  // heavy rows: spmm_heavy
             Quad<V> acc = qzero<V>();
-            group_segment<MODE, WEIGHTED, V>(acc, s, e, gbase, gl, G, col, w, diag, R + mo, ms, lane_ok, hr);
+            group_segment<MODE, WEIGHTED, V, SG>(acc, s, e, gbase, gl, G, col, w, diag, R + mo, ms, lane_ok, hr, sr,
+                                                 quad);
             if (!lane_ok) continue;
             row_epilogue<MODE, V>(i, acc, diag, R, Rp, W, sg, tp, has_prev, mo, ms, s1);
         }
@@ -1177,7 +1272,7 @@ static Layout make_layout(const slaq_graph_s* g, int nv) {
     const int64_t nwin = (g->n + L.rw - 1) / L.rw;
     int64_t nb = (nwin + 3) / 4;
     if (nb < 1) nb = 1;
-    static const int rows_cap = resident_blocks(spmm_rows<SLAQ_LAP_NORMALIZED, false, V>, kSpmmBlock);
+    static const int rows_cap = resident_blocks(spmm_rows<SLAQ_LAP_NORMALIZED, false, V, false>, kSpmmBlock);
     static const int upd_cap = resident_blocks(update<V>, kSpmmBlock);
     const int cap_r = rows_cap < kRowBlocks ? rows_cap : kRowBlocks;
     const int cap_u = upd_cap < kRowBlocks ? upd_cap : kRowBlocks;
@@ -1286,6 +1381,40 @@ static int sweep_grid(int64_t n, int F, int* rows_per_sweep) {
         }                                                                                              \
     } while (0)
 
+// the stage gather kernels with their first-step variant (SG_: sign records)
+#define SLAQ_DISPATCH_SG(MODE_, WEIGHTED_, SG_, KERNEL, ...)                                                \
+    do {                                                                                                     \
+        if (SG_) {                                                                                           \
+            if ((MODE_) == SLAQ_LAP_NORMALIZED) {                                                            \
+                if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, true, V, true>), __VA_ARGS__); \
+                else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, false, V, true>), __VA_ARGS__);          \
+            } else {                                                                                         \
+                if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, true, V, true>), __VA_ARGS__); \
+                else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, false, V, true>), __VA_ARGS__);       \
+            }                                                                                                \
+        } else {                                                                                             \
+            if ((MODE_) == SLAQ_LAP_NORMALIZED) {                                                            \
+                if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, true, V, false>), __VA_ARGS__); \
+                else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_NORMALIZED, false, V, false>), __VA_ARGS__);         \
+            } else {                                                                                         \
+                if (WEIGHTED_) hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, true, V, false>), __VA_ARGS__); \
+                else hipLaunchKernelGGL((KERNEL<SLAQ_LAP_COMBINATORIAL, false, V, false>), __VA_ARGS__);      \
+            }                                                                                                \
+        }                                                                                                    \
+    } while (0)
+
+// Sign-record layout of the first step for ld probe slots: ceil(ld / 32)
+// sign dwords, 4 - sizeof(V)/4 of them per 16-byte slot with the scale, a
+// power of two of slots per record.
+template <typename V>
+static SignRows sign_layout(int ld, int nv) {
+    const int words = (ld + 31) / 32, hw = 4 - (int)(sizeof(V) / 4);
+    const int slots = (words + hw - 1) / hw;
+    int rs = 1;
+    while (rs < slots) rs *= 2;
+    return SignRows{nullptr, 4 * rs, nv};
+}
+
 // diagonal scale of the internal rows in the vectors' precision
 template <typename V> static const V* diag_of(const slaq_graph_s* g);
 template <> const float* diag_of<float>(const slaq_graph_s* g) { return g->diag; }
@@ -1357,10 +1486,18 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
     hipLaunchKernelGGL(state_init<V>, dim3(4), dim3(256), 0, st, nv, m, L.ld, sigma1, alpha, beta, steps, ps, coef,
                        g->stats);
     SLAQ_LAUNCHED();
+    // first step from sign records, kept in the third vector buffer (the
+    // previous basis block, which the first step does not read; the first
+    // update overwrites it after the step's gathers are done)
+    SignRows sr = sign_layout<V>(L.ld, nv);
+    const bool sg1 = g->sign_step != 0 && (size_t)g->n * sr.rd * 4 <= L.off_r[2] - L.off_r[1];
+    if (sg1) sr.rec = (const uint32_t*)Rb[1];
+    CacheWindow cw1 = cw;  // records are narrower: a wider hot window fills the same budget
+    if (g->relabeled) cw1.hot = (int64_t)(kCacheBudget / ((size_t)kColRanges * 4 * sr.rd));
     int rps = 0;
     const int sgrid = sweep_grid(g->n, L.F, &rps);
     hipLaunchKernelGGL(probe_init<V>, dim3(sgrid), dim3(256), 0, st, g->stats, mode, nv, L.F, L.vm, rps, seed, diag,
-                       g->perm, Rb[0]);
+                       g->perm, Rb[0], sg1 ? (uint32_t*)Rb[1] : nullptr, sr.rd);
     SLAQ_LAUNCHED();
 
     int cur = 0, prev = 1;
@@ -1369,18 +1506,20 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
     const int nbp = L.nb_rows + L.nb_heavy;
     for (int j = 1; j <= m; ++j) {
         const int hp = j > 1 ? 1 : 0;
+        const bool sg = sg1 && j == 1;
         for (int tile = 0; tile < L.ntiles; ++tile) {
             if (L.max_pieces > 0) {
                 SLAQ_TIMED("spmm_pieces", st,
-                           SLAQ_DISPATCH(mode, weighted, spmm_pieces, dim3(L.piece_blocks, 1), dim3(256), 0, st,
-                                         g->stats, g->segk, g->segoff, cap, g->col_idx, g->weights, diag, Rb[cur], P,
-                                         L.F, L.vm, L.G, L.K, g->piece, tile, L.TQ, cw));
+                           SLAQ_DISPATCH_SG(mode, weighted, sg, spmm_pieces, dim3(L.piece_blocks, 1), dim3(256), 0, st,
+                                            g->stats, g->segk, g->segoff, cap, g->col_idx, g->weights, diag, Rb[cur],
+                                            P, L.F, L.vm, L.G, L.K, g->piece, tile, L.TQ, sg ? cw1 : cw, sr));
                 SLAQ_LAUNCHED();
             }
             SLAQ_TIMED("spmm_rows", st,
-                       SLAQ_DISPATCH(mode, weighted, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st, g->stats,
-                                     g->row_ptr, g->col_idx, g->weights, diag, g->heavy_min, Rb[cur], Rb[prev],
-                                     Rb[wbuf], coef, hp, part1, nbp, L.F, L.vm, L.G, L.K, L.ld, L.rw, tile, L.TQ, cw));
+                       SLAQ_DISPATCH_SG(mode, weighted, sg, spmm_rows, dim3(L.nb_rows, 1), dim3(kSpmmBlock), 0, st,
+                                        g->stats, g->row_ptr, g->col_idx, g->weights, diag, g->heavy_min, Rb[cur],
+                                        Rb[prev], Rb[wbuf], coef, hp, part1, nbp, L.F, L.vm, L.G, L.K, L.ld, L.rw, tile,
+                                        L.TQ, sg ? cw1 : cw, sr));
             SLAQ_LAUNCHED();
             {  // always launched: its blocks write their (zero) dot partials even without heavy rows
                 SLAQ_TIMED("spmm_heavy", st, {

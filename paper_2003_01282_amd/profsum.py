@@ -89,11 +89,20 @@ def pmc(d, out=sys.stdout):
             print(f"{k:62s} {c:16s} dispatches {len(v):4d} avg {sum(v) / len(v):16.1f}", file=out)
 
 
-def _find(table, stem):
+def _find(table, stem, pool=True):
+    """Counters of the kernels whose names contain stem: every match pooled
+    (template variants of one kernel), or only the first match (dispatch
+    order kept, as the calibration copy needs)."""
+    out = defaultdict(list)
     for k, cs in table.items():
         if stem in k:
-            return cs
-    raise KeyError(stem)
+            for c, v in cs.items():
+                out[c].extend(v)
+            if not pool:
+                break
+    if not out:
+        raise KeyError(stem)
+    return out
 
 
 def calibration_dispatch(values, copy_bytes):
@@ -115,7 +124,7 @@ def traffic(fetch_dir, write_dir, copy_bytes, out_json, settings=None):
     per_launch = 0.0
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         t = pmc_table(d)
-        copy = calibration_dispatch(_find(t, COPY_KERNEL)[counter], copy_bytes)
+        copy = calibration_dispatch(_find(t, COPY_KERNEL, pool=False)[counter], copy_bytes)
         scale = copy_bytes / (copy * 1024.0)  # true bytes per counted byte
         rec[f"{counter}_scale"] = scale
         for k in SPMM_STAGE + (UPDATE_KERNEL,):

@@ -58,6 +58,7 @@ SIGNATURES = {
     "slaq_graph_set_tile": [_vp, _int],
     "slaq_graph_set_cache_rows": [_vp, _i64],
     "slaq_graph_set_fused": [_vp, _int],
+    "slaq_graph_set_sign_step": [_vp, _int],
     "slaq_graph_autotune": [_vp, _int, _int, ctypes.c_uint64, _vp, _vp, _vp, _vp, _sz, _int, ctypes.c_char_p,
                             ctypes.POINTER(_int), _vp],
     "slaq_graph_autotune_workspace": [_vp, _int, _int, ctypes.POINTER(_sz)],
@@ -205,6 +206,11 @@ class Graph:
     def set_fused(self, blocks):
         """slaq_graph_set_fused: -1 automatic, 0 never, 1..256 workgroups."""
         _check(lib().slaq_graph_set_fused(self.handle, int(blocks)))
+
+    def set_sign_step(self, on):
+        """slaq_graph_set_sign_step: first step's gathers from sign records
+        (True, the default) or from the vector rows (False); same results."""
+        _check(lib().slaq_graph_set_sign_step(self.handle, 1 if on else 0))
 
     def settings(self):
         """slaq_graph_settings -> {heavy_min, piece, cache_rows, fused}."""

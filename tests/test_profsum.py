@@ -50,24 +50,29 @@ def test_traffic_scaling(tmp_path):
     copy = "__amd_rocclr_copyBuffer"
     kern = ["void slaq::spmm_pieces<0>(a)", "void slaq::spmm_rows<0>(a)", "void slaq::spmm_heavy<0>(a)",
             "slaq::update<float>(a)"]
+    # another template variant of the light-row kernel: pooled with it
+    variant = "void slaq::spmm_rows<0, false, float, true>(a)"
     write_csv(fetch / "c_counter_collection.csv",
               [{"Kernel_Name": copy, "Counter_Name": "FETCH_SIZE", "Counter_Value": v}
                for v in (524288.0, 2.5, 8218193.5, 262144.0)] +
               [{"Kernel_Name": k, "Counter_Name": "FETCH_SIZE", "Counter_Value": v}
                for k, v in zip(kern, (1000.0, 500.0, 100.0, 50.0))] +
-              [{"Kernel_Name": kern[0], "Counter_Name": "FETCH_SIZE", "Counter_Value": 3000.0}])
+              [{"Kernel_Name": kern[0], "Counter_Name": "FETCH_SIZE", "Counter_Value": 3000.0},
+               {"Kernel_Name": variant, "Counter_Name": "FETCH_SIZE", "Counter_Value": 100.0}])
     write_csv(write / "c_counter_collection.csv",
               [{"Kernel_Name": copy, "Counter_Name": "WRITE_SIZE", "Counter_Value": v}
                for v in (1048576.0, 16436201.0, 0.0625, 530053.0)] +
               [{"Kernel_Name": k, "Counter_Name": "WRITE_SIZE", "Counter_Value": v}
-               for k, v in zip(kern, (10.0, 20.0, 30.0, 40.0))])
+               for k, v in zip(kern, (10.0, 20.0, 30.0, 40.0))] +
+              [{"Kernel_Name": variant, "Counter_Name": "WRITE_SIZE", "Counter_Value": 10.0}])
     out_json = tmp_path / "t.json"
     P.traffic(str(fetch), str(write), float(1 << 30), str(out_json))
     rec = json.loads(out_json.read_text())
     assert abs(rec["FETCH_SIZE_scale"] - 2.0) < 1e-12 and abs(rec["WRITE_SIZE_scale"] - 1.0) < 1e-12
     # spmm_pieces averages its two dispatches: (1000 + 3000) / 2 KiB
     assert rec["kernels"]["spmm_pieces"]["FETCH_SIZE_bytes"] == 2000.0 * 1024 * 2
-    stage = (2000 + 500 + 100) * 1024 * 2 + (10 + 20 + 30) * 1024
+    assert rec["kernels"]["spmm_rows"]["FETCH_SIZE_bytes"] == 300.0 * 1024 * 2
+    stage = (2000 + 300 + 100) * 1024 * 2 + (10 + 15 + 30) * 1024
     assert rec["bytes_per_launch"] == stage
     assert rec["update_bytes_per_launch"] == 50 * 1024 * 2 + 40 * 1024
     assert rec["digest"] == P.kernel_sources_digest()
