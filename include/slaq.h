@@ -403,6 +403,14 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
                             const int64_t* node_off_dev, const int64_t* row_ptr,
                             const int32_t* col_idx, int nv, int m, int nt,
                             const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out);
+/* First step of the global-workspace buckets (graphs whose probe block does
+ * not fit in LDS): with on = 1 (the default) its gathers read a 16-byte
+ * record per column (the Rademacher sign bits of §3.1's probes and the row's
+ * D^-1/2) instead of the row of X_1, expanded in registers to the same
+ * values; results are bit-identical either way.  The records use the
+ * workspace's previous-vector buffer, which the first step does not read.
+ * A captured hipGraph of the plan is dropped when the setting changes. */
+slaq_status slaq_batch_set_sign_step(slaq_batch_t b, int on);
 slaq_status slaq_batch_plan_grown(int64_t n_graphs, const int64_t* node_off, const int64_t* nnz_off,
                                   const int64_t* node_off_dev, const int64_t* row_ptr,
                                   const int32_t* col_idx, int nv, int m, int nt, double growth,

@@ -55,7 +55,33 @@ struct BatchArgs {
     int32_t* steps;         // [G][nv]
     double* trace;          // [G]: tr L
     unsigned* dstat;        // device status word (SLAQ_STATUS_* bits)
+    int sign_first;         // global buckets: first step gathers sign records
 };
+
+// First-step sign records of the global buckets: X_1 is +-1 times one scale
+// per row, so row i's record is a power of two of 16-byte slots, each three
+// dwords of sign bits (bit p of probe p's dword set for -1) and the scale.
+// A gather loads the one slot with the lane's four probes (one cache line,
+// against one or two for the 16 F-byte row) and expands it to exactly X_1's
+// values; row n's record is zero, like X_1's zero row.
+__host__ __device__ inline int sign_slots(int F) {
+    const int need = ((4 * F + 31) / 32 + 2) / 3;
+    int s = 1;
+    while (s < need) s *= 2;
+    return s;
+}
+
+__device__ __forceinline__ float4 sign_expand4(const uint4& r, int p0, int nv) {
+    const int w = p0 >> 5, pos = w % 3;
+    const unsigned wd = pos == 0 ? r.x : (pos == 1 ? r.y : r.z);
+    float v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const unsigned b = __builtin_amdgcn_ubfe(wd, (unsigned)((p0 & 31) + c), 1u);
+        v[c] = __uint_as_float(p0 + c < nv ? (b << 31) | r.w : 0u);
+    }
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
 
 // LDS layout (bytes), n_max nodes, ld = 4F floats per node
 struct BatchLds {
@@ -421,6 +447,7 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
     const int rstride = bact / F;
     float4* const slot = ws + (int64_t)blockIdx.x * 3 * slot_quads;
     float* const dinv = wsd + (int64_t)blockIdx.x * slot_n;
+    const int slots = sign_slots(F), sh = ((4 * q) >> 5) / 3;  // record slots, the lane's slot
 
     for (;;) {
         if (t == 0) {
@@ -442,6 +469,9 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
 
         degrees_and_loops(t, B, n, rp, col, base, dinv, red, &s_nz, &s_loops, &s_corr);
         const uint64_t sg = a.seeds ? a.seeds[g] : a.seed + (uint64_t)g;
+        // the first step's sign records live in the X_{j-1} buffer, which the
+        // first step does not read (the first update overwrites them)
+        uint4* const Rs = (uint4*)P;
         for (int64_t x = t; x < (int64_t)n * F; x += B) {
             const int i = (int)(x / F), qq = (int)(x % F), p0 = 4 * qq;
             const int64_t d = rp[i + 1] - rp[i];
@@ -452,13 +482,21 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
             for (int c = 0; c < 4; ++c)
                 v[c] = (p0 + c < a.nv) ? (((z >> ((p0 & 63) + c)) & 1ull) ? -one : one) : 0.0f;
             X[x] = make_float4(v[0], v[1], v[2], v[3]);
+            if (a.sign_first && (p0 & 31) == 0) {
+                const int w = p0 >> 5;
+                unsigned* sl = (unsigned*)(Rs + (int64_t)i * slots + w / 3);
+                sl[w % 3] = (unsigned)(z >> (p0 & 63));
+                if (w % 3 == 0) sl[3] = __float_as_uint(one);
+            }
         }
         // row n of both rotating buffers stays zero: column ids outside the
-        // graph are clamped to it
+        // graph are clamped to it (and so is row n's sign record)
         for (int x = t; x < F; x += B) {
             X[(int64_t)n * F + x] = make_float4(0.f, 0.f, 0.f, 0.f);
             P[(int64_t)n * F + x] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        if (a.sign_first)
+            for (int x = t; x < slots; x += B) Rs[(int64_t)n * slots + x] = make_uint4(0u, 0u, 0u, 0u);
         init_probe_state(t, B, a.nv, F, a.m, 1.0 / sqrt((double)n), pst, coef);
         double* const gal = a.alpha + (int64_t)g * a.nv * a.m;
         double* const gbe = a.beta + (int64_t)g * a.nv * a.m;
@@ -469,10 +507,39 @@ __global__ void __launch_bounds__(B) batch_slq_global(BatchArgs a, float4* __res
             const float4 tau = make_float4(coef[4 * F + 4 * q], coef[4 * F + 4 * q + 1], coef[4 * F + 4 * q + 2],
                                            coef[4 * F + 4 * q + 3]);
             double s1[4] = {0.0, 0.0, 0.0, 0.0};
+            const bool sgj = a.sign_first && j == 1;
             for (int i = row0; tact && i < n; i += rstride) {
                 const int64_t s = rp[i], e = rp[i + 1];
                 float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
                 int64_t kk = s;
+                if (sgj) {  // first step: gather sign records, expand after each round's loads
+                    const uint4* const Rl = (const uint4*)P + sh;
+                    for (; kk + kBatchUnroll <= e; kk += kBatchUnroll) {
+                        unsigned c[kBatchUnroll];
+#pragma unroll
+                        for (int u = 0; u < kBatchUnroll; ++u)
+                            c[u] = min((unsigned)(int)(col[kk + u] - base), (unsigned)n);
+                        uint4 r[kBatchUnroll];
+#pragma unroll
+                        for (int u = 0; u < kBatchUnroll; ++u) r[u] = Rl[(int64_t)c[u] * slots];
+#pragma unroll
+                        for (int u = 0; u < kBatchUnroll; ++u) {
+                            const float4 x = sign_expand4(r[u], 4 * q, a.nv);
+                            acc.x += x.x;
+                            acc.y += x.y;
+                            acc.z += x.z;
+                            acc.w += x.w;
+                        }
+                    }
+                    for (; kk < e; ++kk) {
+                        const unsigned c = min((unsigned)(int)(col[kk] - base), (unsigned)n);
+                        const float4 x = sign_expand4(Rl[(int64_t)c * slots], 4 * q, a.nv);
+                        acc.x += x.x;
+                        acc.y += x.y;
+                        acc.z += x.z;
+                        acc.w += x.w;
+                    }
+                }
                 for (; kk + kBatchUnroll <= e; kk += kBatchUnroll) {
                     // a column outside the graph reads the zero row n: ignored
                     unsigned c[kBatchUnroll];
@@ -695,6 +762,7 @@ struct slaq_batch_s {
     std::vector<hipEvent_t> joins;
     hipEvent_t fork;
     const uint64_t* seeds;  // caller's per-graph seeds (device) or NULL
+    int sign_step;          // global buckets: first step from sign records (default 1)
     const void* exec_key[9];
     uint64_t exec_seed;
 };
@@ -817,6 +885,7 @@ slaq_status slaq_batch_plan_grown(int64_t n_graphs, const int64_t* node_off, con
     slaq_batch_s* b = new (std::nothrow) slaq_batch_s();
     SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "out of host memory");
     b->G = n_graphs;
+    b->sign_step = 1;
     b->nv = nv;
     b->m = m;
     b->nt = nt;
@@ -980,6 +1049,7 @@ static slaq_status enqueue_batch(slaq_batch_t b, uint64_t seed, const double* t,
         a.steps = sp;
         a.trace = b->tr_dev;
         a.dstat = device_status_word();
+        a.sign_first = b->sign_step;
         SLAQ_REQUIRE(a.dstat, SLAQ_ERR_HIP, "device status word unavailable");
         const int grid = std::min(c.grid, a.count);
         if (c.global) {
@@ -1139,6 +1209,19 @@ slaq_status slaq_batch_set_seeds(slaq_batch_t b, const uint64_t* seeds) {
     clear_error();
     SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
     b->seeds = seeds;
+    return SLAQ_OK;
+}
+
+slaq_status slaq_batch_set_sign_step(slaq_batch_t b, int on) {
+    clear_error();
+    SLAQ_REQUIRE(b, SLAQ_ERR_INVALID_ARG, "batch plan is NULL");
+    SLAQ_REQUIRE(on == 0 || on == 1, SLAQ_ERR_INVALID_ARG, "on must be 0 or 1");
+    if (b->sign_step != on && b->exec) {  // the captured launches carry the old setting
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+    }
+    b->sign_step = on;
     return SLAQ_OK;
 }
 

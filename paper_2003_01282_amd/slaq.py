@@ -84,6 +84,7 @@ SIGNATURES = {
     "slaq_batch_buckets": [_vp, ctypes.POINTER(_int), _vp, _vp, _vp, _vp],
     "slaq_batch_run": [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
     "slaq_batch_set_seeds": [_vp, _vp],
+    "slaq_batch_set_sign_step": [_vp, _int],
     "slaq_batch_workspace": [_vp, ctypes.POINTER(_sz)],
     "slaq_batch_set_workspace": [_vp, _vp, _sz],
     "slaq_batch_autotune": [_vp, _vp, _vp, _vp, _int, _vp, _vp, _vp],
@@ -484,6 +485,11 @@ class Batch:
                 raise SlaqError(SLAQ_ERR_INVALID_ARG, f"seeds needs {self.G} entries")
         self._keep["seeds"] = seeds
         _check(lib().slaq_batch_set_seeds(self.handle, _ptr(seeds)))
+
+    def set_sign_step(self, on):
+        """slaq_batch_set_sign_step: global buckets' first step from sign
+        records (True, the default) or from the rows (False); same results."""
+        _check(lib().slaq_batch_set_sign_step(self.handle, 1 if on else 0))
 
     def buckets(self):
         nb = _int()

@@ -134,3 +134,32 @@ def test_long_recurrence_lds_and_global():
         oh = O.heat_trace(oth, ow2, csr.n, T)
         assert (np.abs(out["heat"][g] - oh) / np.abs(oh)).max() <= TOL_HEAT_REL, g
         np.testing.assert_allclose(out["alpha"][g, :, :3], oa[:, :3], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("nv", [20, 6, 100, 256])
+def test_global_buckets_sign_records_bit_identical(nv):
+    """The global buckets' first step from sign records against the same step
+    gathering the rows of X_1: every coefficient, step count and output equal
+    bit for bit (edgeless, isolated-node and hub members included), also as a
+    replayed hipGraph captured before the setting changed."""
+    print(f"\n[gpu] batched global sign records nv={nv}", flush=True)
+    gs = mixed(9)
+    union, off = inputs.disjoint_union(gs)
+    b = S.batch_plan(union, off, nv=nv, m=8, nt=T.size)
+    t = torch.from_numpy(T).cuda()
+    runs = {}
+    for on in (True, False):
+        b.set_sign_step(on)
+        o = S.batch_run(b, 31, t, heat=True, vnge=True, coeffs=True)
+        torch.cuda.synchronize()
+        runs[on] = {k: v.cpu().numpy() for k, v in o.items()}
+    for k in runs[True]:
+        assert np.array_equal(runs[True][k], runs[False][k]), k
+    # a graph captured with the rows, then the setting flipped: the replay follows it
+    cap = S.batch_run(b, 31, t, graph=True)
+    torch.cuda.synchronize()
+    b.set_sign_step(True)
+    rep = S.batch_run(b, 31, t, graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(rep["heat"].cpu().numpy(), runs[True]["heat"])
+    assert np.array_equal(cap["heat"].cpu().numpy(), runs[False]["heat"])
