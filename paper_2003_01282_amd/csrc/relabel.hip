@@ -294,15 +294,34 @@ __global__ void __launch_bounds__(256) long_row_chunks(int64_t n, const GraphSta
     }
 }
 
-// Row of global chunk g: the largest L with chunk_off[L] <= g (chunk_off is
-// non-decreasing, chunk_off[L + 1] > g for the owning row).
-__device__ __forceinline__ int64_t chunk_row(const int64_t* __restrict__ chunk_off, int64_t n, int64_t g) {
-    int64_t lo = 0, hi = n - 1;
+// Row of global chunk g: the largest L with chunk_off[L] <= g (chunk_off,
+// n + 1 entries, is non-decreasing; chunk_off[L + 1] > g for the owning row).
+// A workgroup walks a contiguous run of chunks, so given the previous
+// chunk's row `prev` (or -1) the row is almost always prev or prev + 1; only
+// otherwise (the run's first chunk, a row without chunks in between) does it
+// search the offsets, from prev + 1 on.
+__device__ __forceinline__ int64_t chunk_row(const int64_t* __restrict__ chunk_off, int64_t n, int64_t g,
+                                             int64_t prev) {
+    int64_t lo = 0;
+    if (prev >= 0) {
+        if (g < chunk_off[prev + 1]) return prev;
+        if (prev + 2 <= n && g < chunk_off[prev + 2]) return prev + 1;
+        lo = prev + 1;
+    }
+    int64_t hi = n - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
         if (chunk_off[mid] <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// The contiguous run of chunks of this workgroup: [*g0, *g1).
+__device__ __forceinline__ void chunk_run(int64_t C, int64_t* g0, int64_t* g1) {
+    const int64_t per = (C + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * per;
+    *g0 = a < C ? a : C;
+    *g1 = a + per < C ? a + per : C;
 }
 
 // Phase 1: each chunk maps its columns to labels (parked in tmp at the row's
@@ -319,10 +338,11 @@ __global__ void __launch_bounds__(256) long_row_count(int64_t n, const int64_t* 
     int64_t bnd[kColRanges];
 #pragma unroll
     for (int r = 0; r < kColRanges; ++r) bnd[r] = bounds[r];
-    const int64_t C = chunk_off[n];
-    for (int64_t g = blockIdx.x; g < C; g += gridDim.x) {
+    int64_t g0, g1, prev = -1;
+    chunk_run(chunk_off[n], &g0, &g1);
+    for (int64_t g = g0; g < g1; ++g) {
         if (threadIdx.x < kColRanges) hist[threadIdx.x] = 0;
-        if (threadIdx.x == 0) row = chunk_row(chunk_off, n, g);
+        if (threadIdx.x == 0) row = prev = chunk_row(chunk_off, n, g, prev);
         __syncthreads();
         const int64_t L = row, q = g - chunk_off[L];
         const int64_t o = perm[L];
@@ -388,9 +408,10 @@ __global__ void __launch_bounds__(256) long_row_place(int64_t n, const int64_t* 
     int64_t bnd[kColRanges];
 #pragma unroll
     for (int r = 0; r < kColRanges; ++r) bnd[r] = bounds[r];
-    const int64_t C = chunk_off[n];
-    for (int64_t g = blockIdx.x; g < C; g += gridDim.x) {
-        if (threadIdx.x == 0) row = chunk_row(chunk_off, n, g);
+    int64_t g0, g1, prev = -1;
+    chunk_run(chunk_off[n], &g0, &g1);
+    for (int64_t g = g0; g < g1; ++g) {
+        if (threadIdx.x == 0) row = prev = chunk_row(chunk_off, n, g, prev);
         __syncthreads();
         const int64_t L = row, q = g - chunk_off[L];
         const int64_t o = perm[L];
