@@ -53,6 +53,7 @@
 namespace slaq {
 
 constexpr int kPieceUnroll = 8;  // gathers in flight per group in the piece kernel
+constexpr int kUpdateRows = 4;   // rows per group with their loads in flight in the update
 
 // breakdown threshold relative to the spectral bound (above the rounding
 // noise of FP32 vectors; the same for FP64 ones, so both stop where the FP64
@@ -689,15 +690,15 @@ __global__ void __launch_bounds__(256) spmm_rows(const GraphStats* __restrict__ 
 }
 
 // R_{j+1} = w - a_j R_j on rows with data (stored when `store`; in the scaled
-// basis for the normalized Laplacian), partial sums of ||R_{j+1}||^2.  Same
-// wave/group layout as spmm_rows.
+// basis for the normalized Laplacian), partial sums of ||R_{j+1}||^2.  Lane
+// groups as in spmm_rows (a row's quads on one group), windows of 64 rows.
 template <typename V>
 __global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st, int laplacian,
                                               const V* __restrict__ diag,
                                               const Quad<V>* __restrict__ W, const Quad<V>* __restrict__ R,
                                               const V* __restrict__ coef, int store,
                                               Quad<V>* __restrict__ Rn, double* __restrict__ part, int nb,
-                                              int F, VecMap vm, int G, int K, int ld, int rw, int tile0, int TQ) {
+                                              int F, VecMap vm, int G, int K, int ld, int tile0, int TQ) {
     constexpr int E = Quad<V>::E;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = lane / G, gl = lane % G;
@@ -713,29 +714,46 @@ __global__ void __launch_bounds__(256) update(const GraphStats* __restrict__ st,
     for (int e = 0; e < E; ++e) s2[e] = 0.0;
     Quad<V> a = qzero<V>();
     if (lane_ok) a = qload(coef + 2 * ld, quad);
+    // a streaming pass: windows of 64 rows (one D^-1/2 load per lane, shared
+    // by lane shuffles), group gi taking rows gi, gi + K, ... of the window,
+    // kUpdateRows of them with their loads in flight together
     const int64_t n = st->n_rows;
-    const int rounds = (rw + K - 1) / K;
-    const int64_t nwin = (n + rw - 1) / rw;
+    const int per = (64 + K - 1) / K;  // rows of a window per group (the last round partly)
+    const int64_t nwin = (n + 63) / 64;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t win = (int64_t)blockIdx.x * 4 + wave; win < nwin; win += nwaves) {
-        const int64_t r0 = win * rw;
+        const int64_t r0 = win * 64;
         const V d_l = r0 + lane < n ? diag[r0 + lane] : V(0);
-        for (int rr = 0; rr < rounds; ++rr) {
-            const int t = rr * K + gi;
-            const V d = __shfl(d_l, t < 64 ? t : 63);
-            const int64_t i = r0 + t;
-            if (!lane_ok || t >= rw || i >= n || d == V(0)) continue;
-            const int64_t at = mo + i * ms;
-            const Quad<V> wv = W[at];
-            const Quad<V> rv = R[at];
-            Quad<V> r;
+        for (int rr = 0; rr < per; rr += kUpdateRows) {
+            bool ok[kUpdateRows];
+            V d[kUpdateRows];
+            int64_t at[kUpdateRows];
+            Quad<V> wv[kUpdateRows], rv[kUpdateRows];
 #pragma unroll
-            for (int e = 0; e < E; ++e) r.v[e] = vfma(-a.v[e], rv.v[e], wv.v[e]);
-            if (store) Rn[at] = r;
-            // normalized: ||R_{j+1}||^2 = sum_i X_{j+1,i}^2 / dinv_i^2
-            const double wgt = laplacian == SLAQ_LAP_NORMALIZED ? 1.0 / ((double)d * (double)d) : 1.0;
+            for (int u = 0; u < kUpdateRows; ++u) {
+                const int t = (rr + u) * K + gi;
+                d[u] = __shfl(d_l, t < 64 ? t : 63);
+                const int64_t i = r0 + t;
+                ok[u] = lane_ok && t < 64 && i < n && d[u] != V(0);
+                at[u] = mo + i * ms;
+            }
 #pragma unroll
-            for (int e = 0; e < E; ++e) s2[e] = fma((double)r.v[e] * (double)r.v[e], wgt, s2[e]);
+            for (int u = 0; u < kUpdateRows; ++u) {
+                wv[u] = ok[u] ? W[at[u]] : qzero<V>();
+                rv[u] = ok[u] ? R[at[u]] : qzero<V>();
+            }
+#pragma unroll
+            for (int u = 0; u < kUpdateRows; ++u) {
+                if (!ok[u]) continue;
+                Quad<V> r;
+#pragma unroll
+                for (int e = 0; e < E; ++e) r.v[e] = vfma(-a.v[e], rv[u].v[e], wv[u].v[e]);
+                if (store) Rn[at[u]] = r;
+                // normalized: ||R_{j+1}||^2 = sum_i X_{j+1,i}^2 / dinv_i^2
+                const double wgt = laplacian == SLAQ_LAP_NORMALIZED ? 1.0 / ((double)d[u] * (double)d[u]) : 1.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) s2[e] = fma((double)r.v[e] * (double)r.v[e], wgt, s2[e]);
+            }
         }
     }
     block_reduce_store<E>(s2, part, nb, F, G, K, ld, tile, TQ);
@@ -1544,7 +1562,7 @@ static slaq_status run_lanczos(slaq_graph_t g, int nv, int m, uint64_t seed, dou
         SLAQ_TIMED("update", st,
                    hipLaunchKernelGGL(update<V>, dim3(L.nb_upd, L.ntiles_u), dim3(kSpmmBlock), 0, st, g->stats,
                                       mode, diag, Rb[wbuf], Rb[cur], coef, j < m ? 1 : 0, Rb[prev], part2, L.nb_upd, L.F,
-                                      L.vm, L.Gu, L.Ku, L.ld, L.rw, 0, kQuadsPerTile));
+                                      L.vm, L.Gu, L.Ku, L.ld, 0, kQuadsPerTile));
         SLAQ_LAUNCHED();
         SLAQ_TIMED("finalize", st,
                    hipLaunchKernelGGL(finalize_b<V>, dim3(nv), dim3(256), 0, st, part2, L.nb_upd, L.ld, m, j,
