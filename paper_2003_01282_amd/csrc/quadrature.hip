@@ -7,15 +7,21 @@
 
 namespace slaq {
 
-// One thread per probe; T_p lives in LDS interleaved across the block
-// (stride = blockDim.x, 3 * blockDim.x * m doubles).
+constexpr int kRitzWaves = 2048;  // probe counts solved one wave per probe
+
+// The first B threads of a block each take one probe; T_p lives in LDS
+// interleaved across them (stride B, 3 * B * m doubles).  With many probes
+// B = blockDim.x (a lane per probe); with few, B = 1 and one wave per probe,
+// since the lanes of a wave run their probes' QR sweeps in lockstep and a
+// wave of divergent lanes takes about the sum of their times (10 probes at
+// m = 15: 181 us as one wave).
 __global__ void __launch_bounds__(64) ritz_kernel(const double* __restrict__ alpha,
                                                           const double* __restrict__ beta,
                                                           const int32_t* __restrict__ steps, int nv, int m,
-                                                          double* __restrict__ theta,
+                                                          int B, double* __restrict__ theta,
                                                           double* __restrict__ tau2, unsigned* dstat) {
     extern __shared__ double lds[];
-    const int t = threadIdx.x, B = blockDim.x;
+    const int t = threadIdx.x;
     const int p = blockIdx.x * B + t;
     double* d = lds + t;
     double* e = lds + B * m + t;
@@ -25,14 +31,14 @@ __global__ void __launch_bounds__(64) ritz_kernel(const double* __restrict__ alp
     {
         const int64_t first = (int64_t)blockIdx.x * B * m;
         const int64_t count = (int64_t)(nv - blockIdx.x * B < B ? nv - blockIdx.x * B : B) * m;
-        for (int64_t x = t; x < count; x += B) {
+        for (int64_t x = t; x < count; x += blockDim.x) {
             const int pl = (int)(x / m), i = (int)(x % m);
             lds[i * B + pl] = alpha[first + x];
             lds[B * m + i * B + pl] = beta[first + x];
         }
     }
     __syncthreads();
-    if (p >= nv) return;
+    if (t >= B || p >= nv) return;
     int k = steps[p];
     k = k < 0 ? 0 : (k > m ? m : k);
     bool finite = true;
@@ -211,10 +217,13 @@ slaq_status slaq_ritz(const double* alpha, const double* beta, const int32_t* st
     SLAQ_REQUIRE(m >= 1 && m <= SLAQ_MAX_STEPS, SLAQ_ERR_INVALID_ARG, "m must be in [1, %d]", SLAQ_MAX_STEPS);
     unsigned* const dstat = device_status_word();
     SLAQ_REQUIRE(dstat, SLAQ_ERR_HIP, "device status word unavailable");
-    const int B = m <= 32 ? 64 : 32;  // keeps the LDS tile at <= 48 KB
+    // up to kRitzWaves probes: a wave each; more: a lane each, 64 (32 for
+    // m > 32: the LDS tile stays at <= 48 KB) per block
+    const int B = nv <= kRitzWaves ? 1 : (m <= 32 ? 64 : 32);
+    const int threads = B == 1 ? 64 : B;
     const size_t lds = (size_t)3 * B * m * sizeof(double);
-    hipLaunchKernelGGL(ritz_kernel, dim3((nv + B - 1) / B), dim3(B), lds,
-                       (hipStream_t)stream, alpha, beta, steps, nv, m, theta, tau2, dstat);
+    hipLaunchKernelGGL(ritz_kernel, dim3((nv + B - 1) / B), dim3(threads), lds,
+                       (hipStream_t)stream, alpha, beta, steps, nv, m, B, theta, tau2, dstat);
     SLAQ_LAUNCHED();
     return SLAQ_OK;
 }
