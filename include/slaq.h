@@ -176,11 +176,12 @@ slaq_status slaq_graph_set_fused(slaq_graph_t g, int blocks);
 /* Gathers of the first Lanczos step (stage kernels).  The first basis block
  * is +-1 per probe times one scale per row (§3.1: Rademacher probes; X_1 =
  * D^-1/2 R_1 for the normalized Laplacian), so with on = 1 (the default) the
- * first step's SpMM reads a compact record per column (the row's sign bits
- * and its scale, padded to a power of two: 8 bytes for up to 32 probes in
- * FP32, 16 for up to 64, 32 for up to 224) instead of its row of vector
- * values, and expands it in registers to the same values: results are
- * bit-identical either way.  The records live in the workspace's third
+ * first step's SpMM reads a compact record per column (16-byte slots of the
+ * row's sign bits and its scale, a power of two of them: one slot for up to
+ * 96 probes in FP32 (64 in FP64), two for up to 192, ...; a gather loads the
+ * one slot with its lane's probes) instead of its row of vector values, and
+ * expands it in registers to the same values: results are bit-identical
+ * either way.  The records live in the workspace's third
  * vector buffer, unused during the first step, so the workspace size does
  * not change.  on = 0 gathers the FP32 rows in every step. */
 slaq_status slaq_graph_set_sign_step(slaq_graph_t g, int on);
@@ -404,10 +405,11 @@ slaq_status slaq_batch_plan(int64_t n_graphs, const int64_t* node_off, const int
                             const int32_t* col_idx, int nv, int m, int nt,
                             const int* bucket_blocks, int n_buckets_cfg, slaq_batch_t* out);
 /* First step of the global-workspace buckets (graphs whose probe block does
- * not fit in LDS): with on = 1 (the default) its gathers read a 16-byte
- * record per column (the Rademacher sign bits of §3.1's probes and the row's
- * D^-1/2) instead of the row of X_1, expanded in registers to the same
- * values; results are bit-identical either way.  The records use the
+ * not fit in LDS): with on = 1 (the default) its gathers read a record per
+ * column (16-byte slots of the Rademacher sign bits of §3.1's probes and the
+ * row's D^-1/2, one slot for up to 96 probes) instead of the row of X_1,
+ * expanded in registers to the same values; results are bit-identical
+ * either way.  The records use the
  * workspace's previous-vector buffer, which the first step does not read.
  * A captured hipGraph of the plan is dropped when the setting changes. */
 slaq_status slaq_batch_set_sign_step(slaq_batch_t b, int on);
