@@ -52,29 +52,26 @@ __device__ inline int tridiag_eig_first_row(double* d, double* e, double* u, int
         // the bulge chase carries d[k], e[k] and u[k] in registers from one
         // rotation to the next (each sweep finalizes index k as it moves on);
         // only the next index is loaded, so the loads do not sit on the
-        // dependent chain of the rotations
+        // dependent chain of the rotations.  The body has no branch but the
+        // rare one for squares out of range (selects instead): a thread
+        // running one rotation after another pays no branch per rotation.
         double a = d[lo * stride], b = e[lo * stride], u0 = u[lo * stride];
+        double bn = 0.0;
         for (int k = lo; k < hi; ++k) {
+            const bool more = k + 1 < hi;
             const double dd = d[(k + 1) * stride];
             const double u1 = u[(k + 1) * stride];
-            const double en = k + 1 < hi ? e[(k + 1) * stride] : 0.0;
+            const double en = more ? e[(k + 1) * stride] : 0.0;
             // rotation with s*x + c*z = 0: the larger of |c|, |s| positive,
             // both from one reciprocal square root of x^2 + z^2 (no division;
             // a ratio-based form guards squares that would over- or underflow)
             double c, s;
             const double r2 = x * x + z * z;
-            if (z == 0.0) {
-                c = 1.0;
-                s = 0.0;
-            } else if (r2 > 1e-290 && r2 < 1e290) {
+            if (r2 > 1e-290 && r2 < 1e290) {
                 const double ri = rsqrt(r2);
-                if (fabs(z) > fabs(x)) {
-                    s = fabs(z) * ri;
-                    c = -x * copysign(ri, z);
-                } else {
-                    c = fabs(x) * ri;
-                    s = -z * copysign(ri, x);
-                }
+                const bool zbig = fabs(z) > fabs(x);
+                s = zbig ? fabs(z) * ri : -z * copysign(ri, x);
+                c = zbig ? -x * copysign(ri, z) : fabs(x) * ri;
             } else if (fabs(z) > fabs(x)) {
                 const double tau = -x / z;
                 s = rsqrt(1.0 + tau * tau);
@@ -84,25 +81,26 @@ __device__ inline int tridiag_eig_first_row(double* d, double* e, double* u, int
                 c = rsqrt(1.0 + tau * tau);
                 s = c * tau;
             }
-            if (k > lo) e[(k - 1) * stride] = c * x - s * z;
+            c = z == 0.0 ? 1.0 : c;
+            s = z == 0.0 ? 0.0 : s;
+            // e[k - 1] is final; at k = lo the store goes to e[lo], which a
+            // later rotation or the sweep's end overwrites
+            e[(k > lo ? k - 1 : k) * stride] = c * x - s * z;
             const double cc = c * c, ss = s * s, cs = c * s;
             d[k * stride] = a * cc - 2.0 * b * cs + dd * ss;
             const double a_next = a * ss + 2.0 * b * cs + dd * cc;
-            const double bn = (a - dd) * cs + b * (cc - ss);
+            bn = (a - dd) * cs + b * (cc - ss);
             u[k * stride] = c * u0 - s * u1;
             const double u_next = s * u0 + c * u1;
-            if (k + 1 < hi) {
-                z = -s * en;
-                b = c * en;
-                x = bn;
-            } else {
-                e[k * stride] = bn;
-                d[(k + 1) * stride] = a_next;
-                u[(k + 1) * stride] = u_next;
-            }
+            z = more ? -s * en : z;
+            b = more ? c * en : b;
+            x = more ? bn : x;
             a = a_next;
             u0 = u_next;
         }
+        e[(hi - 1) * stride] = bn;
+        d[hi * stride] = a;
+        u[hi * stride] = u0;
     }
     return sweeps;
 }
